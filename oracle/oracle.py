@@ -1,0 +1,320 @@
+"""Python view of the CPU oracle (TEST INFRASTRUCTURE).
+
+The oracle is the plain sequential model that the GPU library is checked
+against. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import this module. The product path never does.
+
+The arithmetic lives in ``nfm_oracle.c``; this module only marshals numpy
+arrays and strings the per-iteration steps of the weight recursion together
+in the order the method prescribes (weights -> sample -> update, Sec. II of
+Muller/Schnabel/Janke, arXiv:2011.08560).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "nfm_oracle.c")
+LIB = os.path.join(HERE, "libnfm_oracle.so")
+
+PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
+TAG_ACC, TAG_SPIN, TAG_J, TAG_PT, TAG_SWAP = 1, 2, 3, 4, 5
+
+WALKER_DTYPE = np.dtype(
+    [
+        ("E", np.int32),
+        ("E_min", np.int32),
+        ("rt_state", np.int32),
+        ("new_min", np.int32),
+        ("rt_count", np.uint64),
+        ("t_first", np.uint64),
+        ("t_last", np.uint64),
+    ],
+    align=True,
+)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, so fp64 sums match the
+    operation order written in the source)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+               "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        P = np.ctypeslib.ndpointer
+        i32, u32, u64, i64, dbl = C.c_int32, C.c_uint32, C.c_uint64, C.c_int64, C.c_double
+        L.orc_philox4x32_10.argtypes = [P(np.uint32), P(np.uint32), P(np.uint32)]
+        L.orc_n_minus.argtypes = [i32, P(np.int8)]
+        L.orc_n_minus.restype = i32
+        L.orc_e_base.argtypes = [i32, P(np.int8)]
+        L.orc_e_base.restype = i32
+        L.orc_n_levels.argtypes = [i32, P(np.int8)]
+        L.orc_n_levels.restype = i32
+        L.orc_sweep_order.argtypes = [i32, P(np.int32)]
+        L.orc_gen_couplings.argtypes = [i32, u64, u32, P(np.int8)]
+        L.orc_gen_spins.argtypes = [i32, u64, u32, u32, P(np.int8)]
+        L.orc_energy.argtypes = [i32, P(np.int8), P(np.int8)]
+        L.orc_energy.restype = i32
+        L.orc_unsatisfied.argtypes = [i32, P(np.int8), P(np.int8), i32]
+        L.orc_unsatisfied.restype = i32
+        L.orc_table_rows.argtypes = [i32, i32, i32, C.POINTER(i32)]
+        L.orc_table_rows.restype = i32
+        L.orc_build_thresholds.argtypes = [i32, P(np.float64), i32, i32, P(np.uint32),
+                                           C.POINTER(i32), C.POINTER(i32)]
+        L.orc_build_thresholds.restype = i32
+        L.orc_track.argtypes = [C.c_void_p, i32, i32, i32, u64]
+        L.orc_muca_sweeps.argtypes = [i32, P(np.int8), P(np.int8), C.c_void_p, P(np.uint32), i32, i32,
+                                      i32, i32, u64, u32, u32, u64, u64, C.c_void_p, C.c_void_p, i32]
+        L.orc_muca_sweeps.restype = i32
+        L.orc_brute_dos.argtypes = [i32, P(np.int8), P(np.uint64)]
+        L.orc_brute_dos.restype = i32
+        L.orc_power_profile.argtypes = [dbl, dbl, dbl, dbl]
+        L.orc_power_profile.restype = dbl
+        L.orc_rec_weights.argtypes = [i32, i32, i32, i32, i32, dbl, dbl, P(np.float64),
+                                      P(np.float64), P(np.float64), P(np.float64)]
+        L.orc_rec_update.argtypes = [i32, i32, i32, i32, P(np.float64), P(np.float64), P(np.uint64),
+                                     P(np.float64), P(np.float64), P(np.uint8), C.POINTER(i32),
+                                     C.POINTER(dbl)]
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------- basic wrappers
+
+def philox(ctr, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(np.ascontiguousarray(ctr, np.uint32), np.ascontiguousarray(key, np.uint32), out)
+    return out
+
+
+def couplings(L: int, seed: int, real_id: int) -> np.ndarray:
+    J = np.zeros(3 * L ** 3, np.int8)
+    lib().orc_gen_couplings(L, seed, real_id, J)
+    return J
+
+
+def spins(L: int, seed: int, real_id: int, walker: int) -> np.ndarray:
+    S = np.zeros(L ** 3, np.int8)
+    lib().orc_gen_spins(L, seed, real_id, walker, S)
+    return S
+
+
+def energy(L: int, J: np.ndarray, S: np.ndarray) -> int:
+    return int(lib().orc_energy(L, np.ascontiguousarray(J, np.int8), np.ascontiguousarray(S, np.int8)))
+
+
+def unsatisfied(L: int, J: np.ndarray, S: np.ndarray, i: int) -> int:
+    return int(lib().orc_unsatisfied(L, J, S, i))
+
+
+def e_base(L: int, J: np.ndarray) -> int:
+    return int(lib().orc_e_base(L, J))
+
+
+def n_levels(L: int, J: np.ndarray) -> int:
+    return int(lib().orc_n_levels(L, J))
+
+
+def n_minus(L: int, J: np.ndarray) -> int:
+    return int(lib().orc_n_minus(L, J))
+
+
+def sweep_order(L: int) -> np.ndarray:
+    o = np.zeros(L ** 3, np.int32)
+    lib().orc_sweep_order(L, o)
+    return o
+
+
+def level_of(E: int, eb: int) -> int:
+    return (E - eb) // 4
+
+
+def table_rows(K: int, k_lo: int, k_top: int):
+    row0 = C.c_int32()
+    rows = lib().orc_table_rows(K, k_lo, k_top, C.byref(row0))
+    return row0.value, rows
+
+
+def build_thresholds(K: int, lnw_levels: np.ndarray, k_lo: int, k_top: int):
+    """lnw_levels: log-weights on levels k_lo..k_top. Returns (thr[rows, 8], row0)."""
+    lnw = np.ascontiguousarray(lnw_levels, np.float64)
+    assert lnw.shape[0] == k_top - k_lo + 1
+    row0, rows = table_rows(K, k_lo, k_top)
+    thr = np.zeros(rows * 8, np.uint32)
+    r0, nr = C.c_int32(), C.c_int32()
+    rc = lib().orc_build_thresholds(K, lnw, k_lo, k_top, thr, C.byref(r0), C.byref(nr))
+    if rc != 0:
+        raise ValueError("bad level range")
+    return thr.reshape(nr.value, 8), r0.value
+
+
+def new_walkers(n: int, E0) -> np.ndarray:
+    w = np.zeros(n, WALKER_DTYPE)
+    w["E"] = E0
+    w["E_min"] = E0
+    return w
+
+
+def track(w: np.ndarray, E: int, e_bot: int, e_top: int, tau: int) -> None:
+    lib().orc_track(w.ctypes.data, E, e_bot, e_top, tau)
+
+
+def muca_sweeps(L, J, S, w, thr, row0, e_bot, e_top, walker_seed, real_id, walker,
+                t0, n_sweeps, hist=None, trace=None, check_energy=False):
+    """Run n_sweeps for one walker in place (S: int8[N], w: one-element WALKER_DTYPE array)."""
+    thr = np.ascontiguousarray(thr, np.uint32).reshape(-1)
+    rows = thr.shape[0] // 8
+    rc = lib().orc_muca_sweeps(L, J, S, w.ctypes.data, thr, row0, rows, e_bot, e_top,
+                               walker_seed, real_id, walker, t0, n_sweeps,
+                               None if hist is None else hist.ctypes.data,
+                               None if trace is None else trace.ctypes.data,
+                               1 if check_energy else 0)
+    if rc == -1:
+        raise AssertionError("incremental energy disagrees with recomputation")
+    if rc != 0:
+        raise RuntimeError("oracle sweep failed")
+
+
+def brute_dos(L: int, J: np.ndarray) -> np.ndarray:
+    g = np.zeros(n_levels(L, J), np.uint64)
+    if lib().orc_brute_dos(L, J, g) != 0:
+        raise ValueError("lattice too large for enumeration")
+    return g
+
+
+def power_profile(E, E_g, dE, alpha) -> float:
+    return float(lib().orc_power_profile(E, E_g, dE, alpha))
+
+
+def rec_weights(K, eb, k_lo, k_top, profile, pl_dE, pl_alpha, b):
+    S = np.zeros(K, np.float64)
+    lnP = np.zeros(K, np.float64)
+    lnW = np.zeros(K, np.float64)
+    lib().orc_rec_weights(K, eb, k_lo, k_top, profile, pl_dE, pl_alpha,
+                          np.ascontiguousarray(b, np.float64), S, lnP, lnW)
+    return S, lnP, lnW
+
+
+def rec_update(K, k_lo_used, k_top, k_min_seen, lnW_used, lnP_used, H, b, p, visited):
+    """In-place update of b, p, visited. Returns (k_lo_new, flatness)."""
+    kl = C.c_int32()
+    fl = C.c_double()
+    lib().orc_rec_update(K, k_lo_used, k_top, k_min_seen, lnW_used, lnP_used,
+                         np.ascontiguousarray(H, np.uint64), b, p, visited, C.byref(kl), C.byref(fl))
+    return kl.value, fl.value
+
+
+# --------------------------------------------------------------------------- weight iteration
+
+@dataclass
+class Realization:
+    """One disorder realization with its walkers, as the oracle sees it."""
+    L: int
+    J: np.ndarray
+    real_id: int
+    walker_seed: int
+    S: np.ndarray          # int8 [W, N]
+    w: np.ndarray          # WALKER_DTYPE [W]
+    t: int = 0             # absolute sweep counter
+
+    @property
+    def N(self):
+        return self.L ** 3
+
+    @property
+    def eb(self):
+        return e_base(self.L, self.J)
+
+    @property
+    def K(self):
+        return n_levels(self.L, self.J)
+
+    @property
+    def k_top(self):
+        """Lowest level with E >= 0 (the 'highest energy' end, Sec. III)."""
+        return -(self.eb) // 4 if (-self.eb) % 4 == 0 else -(self.eb) // 4 + 1
+
+
+def make_realization(L, disorder_seed, real_id, walker_seed, walkers) -> Realization:
+    J = couplings(L, disorder_seed, real_id)
+    S = np.stack([spins(L, walker_seed, real_id, w) for w in range(walkers)])
+    E0 = np.array([energy(L, J, S[w]) for w in range(walkers)], np.int32)
+    return Realization(L, J, real_id, walker_seed, S, new_walkers(walkers, E0))
+
+
+def sample(rz: Realization, thr, row0, e_bot, e_top, n_sweeps, trace=False):
+    """Run every walker n_sweeps; returns (pooled histogram, traces or None)."""
+    H = np.zeros(rz.K, np.uint64)
+    tr = np.zeros((rz.S.shape[0], n_sweeps), np.int32) if trace else None
+    for wk in range(rz.S.shape[0]):
+        ws = rz.w[wk:wk + 1].copy()
+        Sw = rz.S[wk].copy()
+        muca_sweeps(rz.L, rz.J, Sw, ws, thr, row0, e_bot, e_top, rz.walker_seed, rz.real_id, wk,
+                    rz.t, n_sweeps, hist=H, trace=None if tr is None else tr[wk])
+        rz.S[wk] = Sw
+        rz.w[wk] = ws[0]
+    rz.t += n_sweeps
+    return H, tr
+
+
+@dataclass
+class RecursionState:
+    b: np.ndarray
+    p: np.ndarray
+    visited: np.ndarray
+    k_lo: int
+    k_top: int
+
+
+def recursion_init(rz: Realization) -> RecursionState:
+    K = rz.K
+    k_lo = min(int(level_of(int(e), rz.eb)) for e in rz.w["E_min"])
+    return RecursionState(np.zeros(K), np.zeros(K), np.zeros(K, np.uint8), min(k_lo, rz.k_top), rz.k_top)
+
+
+def weight_iterations(rz: Realization, st: RecursionState, n_iter: int, n_sweeps: int,
+                      profile=PROFILE_FLAT, pl_dE=1.0, pl_alpha=0.0, f_tol=0.5, stop=True):
+    """The weight iteration (Sec. II): build weights from the DOS estimate and the
+    target profile, sample, update the estimate; stop at the first iteration whose
+    histogram is flat to f_tol with no new minimum. Returns a list of per-iteration
+    records (k_lo, flatness, converged)."""
+    log = []
+    for it in range(n_iter):
+        S, lnP, lnW = rec_weights(rz.K, rz.eb, st.k_lo, st.k_top, profile, pl_dE, pl_alpha, st.b)
+        thr, row0 = build_thresholds(rz.K, lnW[st.k_lo:st.k_top + 1], st.k_lo, st.k_top)
+        e_lo = rz.eb + 4 * st.k_lo
+        H, _ = sample(rz, thr, row0, e_lo, 0, n_sweeps)
+        k_min = int(level_of(int(rz.w["E_min"].min()), rz.eb))
+        k_lo_old = st.k_lo
+        st.k_lo, flat = rec_update(rz.K, st.k_lo, st.k_top, min(k_min, st.k_lo), lnW, lnP, H,
+                                   st.b, st.p, st.visited)
+        conv = flat >= f_tol and st.k_lo == k_lo_old
+        log.append((it, st.k_lo, flat, conv))
+        if conv and stop:
+            break
+    return log
+
+
+def production_weights(rz: Realization, st: RecursionState, kind: str, pl_dE=96.0, pl_alpha=-3.6):
+    """Production ensembles from the final estimate (Sec. II): flat lnW = -S,
+    power law -S + ln P_SH, 1/k -S + (S - ln sum exp S). Returns lnW on levels."""
+    prof = {"flat": PROFILE_FLAT, "power": PROFILE_POWER, "invk": PROFILE_INVK}[kind]
+    S, lnP, lnW = rec_weights(rz.K, rz.eb, st.k_lo, st.k_top, prof, pl_dE, pl_alpha, st.b)
+    return lnW
