@@ -1,0 +1,196 @@
+/*
+ * nfm.h -- C ABI of libnfm: multicanonical (MUCA) sampling of the 3D bimodal
+ * Edwards-Anderson spin glass on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: F. Muller, S. Schnabel, W. Janke, "Nonflat Histogram Techniques for
+ * Spin Glasses" (arXiv:2011.08560).
+ *   Model            Sec. II, Eq. (1): H = -sum_<ij> J_ij S_i S_j, S, J in {+1,-1},
+ *                    simple-cubic lattice L^3 with periodic boundaries, 3V couplings
+ *                    drawn +-1 with probability 1/2 and then quenched.
+ *   Update           Sec. II, Eq. (2): single-spin Metropolis with acceptance
+ *                    min(1, W(E_new)/W(E_old)) for energy weights W(E).
+ *   Weights          Sec. II, Eqs. (3)-(7): flat W ~ 1/Omega, power law
+ *                    W ~ P_SH/Omega with Eq. (5), 1/k-ensemble Eq. (7).
+ *   Round trips      Sec. III: E ~ 0 -> lowest energy found -> E ~ 0.
+ *
+ * Conventions (all fixed by this header; every implementation must follow them):
+ *   site           i = x + L*y + L*L*z, 0 <= x,y,z < L;
+ *   couplings      3 planes of N = L^3 bits, plane d in {0:x,1:y,2:z}; bit i of
+ *                  plane d is the bond between i and i+e_d; bit set <=> J = -1;
+ *                  packed LSB-first into uint32 words, each plane padded to
+ *                  JW = ceil(N/32) words (3*JW words per realization);
+ *   spins          int8 +1/-1 per site at the ABI;
+ *   energy levels  k = (E - e_base)/4, e_base = -3N + 2*(n_minus mod 2), where
+ *                  n_minus is the number of J = -1 bonds; K = (3N - e_base)/4 + 1;
+ *   sweep          N attempts in checkerboard order: every site with x+y+z even
+ *                  (ascending i), then every odd one. Sweep t has attempt stamps
+ *                  t*N + a + 1 for attempt a = 0..N-1;
+ *   random words   Philox4x32-10 (Salmon et al., SC'11). The attempt at the q-th
+ *                  site of colour c in plane z (q = y*L/2 + x/2) of sweep t, walker w
+ *                  of realization id r uses output[q & 3] of counter
+ *                  (((c*L + z) << 8) | (q >> 2), t, r, (w << 8) | 1) under
+ *                  key = (walker_seed low, high) 32-bit halves;
+ *   thresholds     a table row per level, 8 uint32 per row: entry u = 0..6 is the
+ *                  acceptance threshold of a flip with u unsatisfied bonds
+ *                  (Delta E = 12 - 4u); a move is accepted iff thr == 0xFFFFFFFF
+ *                  or r < thr for the attempt's random word r. A compact table
+ *                  holds rows [row0, row0+rows); lookups clamp the level into it.
+ *
+ * Memory and streams: the caller owns all device memory. nfm_workspace_bytes()
+ * returns the size of one device buffer; the caller allocates it (e.g. a torch
+ * tensor) and passes its address to nfm_create(). Every kernel of a context is
+ * launched on the HIP stream given at creation. Host arrays passed to the API
+ * are borrowed for the duration of the call only. Functions named nfm_get_* /
+ * nfm_read_* synchronize the stream; the others are asynchronous unless stated.
+ *
+ * Errors: every function returns an nfm_status. Invalid arguments return
+ * NFM_EINVAL and change no state; nfm_last_error() describes the last failure.
+ * No C++ exception crosses this boundary.
+ */
+#ifndef NFM_H
+#define NFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NFM_OK = 0,
+  NFM_EINVAL = -1,   /* invalid argument (unsupported L, bad range, null pointer) */
+  NFM_ERANGE = -2,   /* value out of the representable range (sweep counter, sizes) */
+  NFM_EDEVICE = -3,  /* HIP runtime error */
+  NFM_ESTATE = -4,   /* call not valid in the current state */
+  NFM_ESIZE = -5     /* workspace too small */
+} nfm_status;
+
+typedef struct nfm_ctx nfm_ctx;
+
+/* Batch description. All realizations of a context share the seeds; realization
+ * r (0-based in the batch) has id first_real_id + r in the random streams. */
+typedef struct {
+  int32_t n_real;            /* realizations in the batch, >= 1 */
+  const int32_t* L;          /* host [n_real]: linear size; even, 2 <= L <= 12 */
+  const int32_t* walkers;    /* host [n_real]: walkers per realization, multiple of 64 */
+  uint64_t disorder_seed;    /* Philox key of the couplings */
+  uint64_t walker_seed;      /* Philox key of initial spins and acceptance words */
+  uint32_t first_real_id;
+  int32_t trace_capacity;    /* sweeps of per-walker energy trace kept (0 = none) */
+} nfm_batch_desc;
+
+/* Per-walker state as read back (host layout, 40 bytes). */
+typedef struct {
+  int32_t E;          /* current energy */
+  int32_t E_min;      /* lowest energy seen */
+  int32_t rt_state;   /* 0: top not reached yet, 1: at/after top, 2: bottom after top */
+  int32_t new_min;    /* 1 once an energy below e_bot was seen (sample must be rerun) */
+  uint64_t rt_count;  /* completed round trips */
+  uint64_t t_first;   /* attempt stamp of the first arrival at the top */
+  uint64_t t_last;    /* attempt stamp of the last completed round trip */
+} nfm_walker_stats;
+
+/* Per-realization integer sums over its walkers (host layout, 40 bytes). */
+typedef struct {
+  uint64_t rt_count;  /* sum of rt_count */
+  uint64_t rt_time;   /* sum over walkers with rt_count > 0 of (t_last - t_first), attempts */
+  int32_t E_min;      /* minimum of E_min */
+  int32_t new_min;    /* OR of new_min */
+  int32_t walkers_with_trips;
+  int32_t pad;
+  uint64_t reserved;
+} nfm_real_stats;
+
+/* Size of the device workspace for a batch. Sec. II (model sizes). */
+nfm_status nfm_workspace_bytes(const nfm_batch_desc* desc, size_t* bytes);
+
+/* Create a context over a caller-owned device workspace of at least
+ * nfm_workspace_bytes() bytes (256-byte aligned) on device `device`, launching on
+ * `hip_stream` (a hipStream_t; NULL = default stream). The workspace is not freed
+ * by the library. */
+nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_workspace,
+                      size_t workspace_bytes, int device, void* hip_stream);
+void nfm_destroy(nfm_ctx* ctx);
+const char* nfm_last_error(const nfm_ctx* ctx);
+
+/* Geometry queries (host-side, no synchronization). */
+int32_t nfm_n_real(const nfm_ctx* ctx);
+int64_t nfm_n_walkers(const nfm_ctx* ctx);              /* total walkers of the batch */
+int32_t nfm_levels(const nfm_ctx* ctx, int32_t r);      /* K of realization r (after couplings) */
+int32_t nfm_e_base(const nfm_ctx* ctx, int32_t r);      /* e_base of realization r */
+int64_t nfm_level_offset(const nfm_ctx* ctx, int32_t r);/* start of r in histogram / level arrays */
+int64_t nfm_levels_total(const nfm_ctx* ctx);           /* sum of K over the batch */
+int64_t nfm_walker_offset(const nfm_ctx* ctx, int32_t r);/* global index of r's first walker */
+uint64_t nfm_sweep_counter(const nfm_ctx* ctx);         /* sweeps done so far */
+
+/* Couplings. Sec. II: 3V couplings +-1 with p = 1/2, drawn once per realization.
+ * nfm_init_couplings draws them on the device: bit c (c = d*N + i) is bit c%32 of
+ * output[m & 3] of counter (m >> 2, id, 0, 3), m = c/32, key = disorder_seed.
+ * nfm_set_couplings / nfm_get_couplings copy realizations [r0, r0+count) in the
+ * ABI layout (3*JW words each, host). Setting couplings resets the energy levels,
+ * tables and histograms of those realizations; call nfm_compute_energies after
+ * changing spins or couplings. */
+nfm_status nfm_init_couplings(nfm_ctx* ctx);
+nfm_status nfm_set_couplings(nfm_ctx* ctx, int32_t r0, int32_t count, const uint32_t* host_words);
+nfm_status nfm_get_couplings(nfm_ctx* ctx, int32_t r0, int32_t count, uint32_t* host_words);
+
+/* Spins. nfm_init_spins draws every walker's start: bit i is bit i%32 of
+ * output[m & 3] of counter (m >> 2, 0, id, (w << 8) | 2), m = i/32, key =
+ * walker_seed; set bit <=> S = -1. Set/get copy walkers [w0, w0+count) (global
+ * walker index; realization r owns [nfm_walker_offset(r), +walkers[r])), N int8 each.
+ * Spins of walkers of different L cannot be mixed in one call. */
+nfm_status nfm_init_spins(nfm_ctx* ctx);
+nfm_status nfm_set_spins(nfm_ctx* ctx, int64_t w0, int64_t count, const int8_t* host_spins);
+nfm_status nfm_get_spins(nfm_ctx* ctx, int64_t w0, int64_t count, int8_t* host_spins);
+
+/* Eq. (1) for every walker; resets E_min = E, round-trip state, counters and
+ * new_min of every walker. */
+nfm_status nfm_compute_energies(nfm_ctx* ctx);
+
+/* Tables. nfm_set_thresholds copies a raw table for realization r: rows x 8
+ * uint32 (host) covering levels [row0, row0+rows); 1 <= rows <= K.
+ * nfm_set_weights_lnw builds the tables of all realizations on the device from
+ * log-weights: host lnw holds, for each realization, K doubles indexed by level
+ * (only [k_lo[r], k_top[r]] is read); the table covers
+ * [max(0,k_lo-3), min(K-1,k_top+3)] with step log-weights d(j) = lnw(j+1)-lnw(j)
+ * on [k_lo, k_top), d(j) = 0 for j >= k_top, d(j) = d(k_lo) for j < k_lo; entry
+ * (k,u), m = 3-u: x = exp(d(k)+..+d(k+m-1)) (m>0), exp(-(d(k+m)+..+d(k-1))) (m<0),
+ * 1 (m=0), sums in ascending j; thr = 0xFFFFFFFF if x >= 1 else floor(x*2^32).
+ * Eq. (2) with weights from Eqs. (3)-(7). */
+nfm_status nfm_set_thresholds(nfm_ctx* ctx, int32_t r, const uint32_t* host_thr, int32_t row0,
+                              int32_t rows);
+nfm_status nfm_get_thresholds(nfm_ctx* ctx, int32_t r, uint32_t* host_thr, int32_t* row0,
+                              int32_t* rows);
+nfm_status nfm_set_weights_lnw(nfm_ctx* ctx, const double* host_lnw, const int32_t* k_lo,
+                               const int32_t* k_top);
+
+/* Round-trip bounds of realization r (Sec. III): the top is E >= e_top, the bottom
+ * E <= e_bot; an energy below e_bot sets new_min. Default: e_top = 0 and
+ * e_bot = e_base - 4 (no bottom). Takes effect at the next nfm_run_sweeps. */
+nfm_status nfm_set_rt_bounds(nfm_ctx* ctx, int32_t r, int32_t e_bot, int32_t e_top);
+
+/* Run n_sweeps sweeps of every walker (asynchronous). After every attempt the
+ * walker's minimum and round-trip state are updated (stamp t*N + a + 1); after
+ * every sweep its level is added to its realization's histogram and its energy
+ * to its trace (while fewer than trace_capacity sweeps have been traced since
+ * the last nfm_reset_trace). Sec. II, Eq. (2); Sec. III. */
+nfm_status nfm_run_sweeps(nfm_ctx* ctx, uint64_t n_sweeps);
+
+/* Histograms: sum over realizations of K uint64 (level order), accumulated since
+ * the last reset. reset != 0 clears them after reading. */
+nfm_status nfm_read_histograms(nfm_ctx* ctx, uint64_t* host_dst, int reset);
+nfm_status nfm_reset_histograms(nfm_ctx* ctx);
+nfm_status nfm_read_walkers(nfm_ctx* ctx, nfm_walker_stats* host_dst);   /* all walkers */
+nfm_status nfm_read_realizations(nfm_ctx* ctx, nfm_real_stats* host_dst); /* all realizations */
+/* Trace: walkers x trace_capacity int32 (walker-major); entry s is the energy
+ * after the s-th traced sweep; *n_valid receives the number of traced sweeps. */
+nfm_status nfm_read_trace(nfm_ctx* ctx, int32_t* host_dst, int32_t* n_valid);
+nfm_status nfm_reset_trace(nfm_ctx* ctx);
+
+nfm_status nfm_sync(nfm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NFM_H */

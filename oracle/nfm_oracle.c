@@ -229,9 +229,22 @@ void orc_track(orc_walker* w, int32_t E, int32_t e_bot, int32_t e_top, uint64_t 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Multicanonical sweeps, Eq. (2). One sweep = N attempts in checkerboard order;
- * attempt a of sweep t draws output[a & 3] of Philox counter
- * (a >> 2, t, real_id, (walker << 8) | TAG_ACC) under key = walker seed.
+/* Random word of an attempt: the site's colour c = (x+y+z) mod 2, its plane z and
+ * its rank q among the colour-c sites of plane z in ascending i select
+ * output[q & 3] of Philox counter (((c L + z) << 8) | (q >> 2), t, real_id,
+ * (walker << 8) | TAG_ACC) under key = walker seed.                          */
+static void site_rng_slot(int32_t L, int32_t i, uint32_t* ctr0, int32_t* which) {
+  int32_t x = i % L, y = (i / L) % L, z = i / (L * L);
+  int32_t c = (x + y + z) % 2;
+  int32_t q = 0;
+  for (int32_t yy = 0; yy < L; ++yy)
+    for (int32_t xx = 0; xx < L; ++xx)
+      if ((xx + yy + z) % 2 == c && xx + L * yy < x + L * y) ++q;
+  *ctr0 = ((uint32_t)(c * L + z) << 8) | (uint32_t)(q >> 2);
+  *which = q & 3;
+}
+
+/* Multicanonical sweeps, Eq. (2). One sweep = N attempts in checkerboard order.
  * The table row of level k is clamped into [row0, row0+rows-1]. After every
  * attempt the round-trip tracker sees the energy with stamp t N + a + 1; after
  * every sweep the energy level is histogrammed and traced.                  */
@@ -244,8 +257,14 @@ int32_t orc_muca_sweeps(int32_t L, const int8_t* J, int8_t* S, orc_walker* w,
   int32_t N = L * L * L;
   int32_t e_base = orc_e_base(L, J);
   int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
-  if (!order) return -2;
+  uint32_t* slot_ctr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
+  int32_t* slot_which = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  if (!order || !slot_ctr || !slot_which) {
+    free(order); free(slot_ctr); free(slot_which);
+    return -2;
+  }
   orc_sweep_order(L, order);
+  for (int32_t i = 0; i < N; ++i) site_rng_slot(L, i, &slot_ctr[i], &slot_which[i]);
   int32_t status = 0;
   for (uint64_t t = t0; t < t0 + n_sweeps; ++t) {
     for (int32_t a = 0; a < N; ++a) {
@@ -256,8 +275,8 @@ int32_t orc_muca_sweeps(int32_t L, const int8_t* J, int8_t* S, orc_walker* w,
       if (row < 0) row = 0;
       if (row > rows - 1) row = rows - 1;
       uint32_t th = thr[row * 8 + u];
-      uint32_t r = philox_word((uint32_t)a >> 2, (uint32_t)t, real_id,
-                               (walker << 8) | ORC_TAG_ACC, walker_seed, a & 3);
+      uint32_t r = philox_word(slot_ctr[i], (uint32_t)t, real_id,
+                               (walker << 8) | ORC_TAG_ACC, walker_seed, slot_which[i]);
       int accept = (th == 0xFFFFFFFFu) || (r < th);
       if (accept) {
         S[i] = (int8_t)(-S[i]);
@@ -270,6 +289,8 @@ int32_t orc_muca_sweeps(int32_t L, const int8_t* J, int8_t* S, orc_walker* w,
     if (trace) trace[t - t0] = w->E;
   }
   free(order);
+  free(slot_ctr);
+  free(slot_which);
   return status;
 }
 

@@ -16,9 +16,11 @@
  *   sweep order  checkerboard: all sites with x+y+z even in ascending i, then
  *                all odd ones; attempt a = 0..N-1 counts position in that order;
  *   random words Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11);
- *                acceptance word for attempt a of sweep t of walker w of
- *                realization r: output[a & 3] of counter
- *                (a >> 2, t, r, (w << 8) | TAG_ACC) under key = walker seed.
+ *                the acceptance word of the attempt at the q-th site of colour c
+ *                in plane z (rank among that colour's sites of the plane, ascending
+ *                i) in sweep t of walker w of realization r is output[q & 3] of
+ *                counter (((c L + z) << 8) | (q >> 2), t, r, (w << 8) | TAG_ACC)
+ *                under key = walker seed.
  */
 #ifndef NFM_ORACLE_H
 #define NFM_ORACLE_H

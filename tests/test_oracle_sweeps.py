@@ -267,3 +267,26 @@ def test_round_trip_tracker_synthetic(orc):
         orc.track(w, e, e_bot, e_top, s)
     assert w["rt_count"][0] == 1 and w["t_first"][0] == 3 and w["t_last"][0] == 6
     assert w["new_min"][0] == 0
+
+
+def test_acceptance_word_layout(orc):
+    """With every threshold equal to 2^31 an attempt is accepted iff its random
+    word is below 2^31, whatever the state, so one sweep flips exactly the sites
+    whose word (re-derived here from the documented counter layout) is small."""
+    for L in (2, 3, 4, 6):
+        N = L ** 3
+        J = orc.couplings(L, 1, 0)
+        K = orc.n_levels(L, J)
+        S0 = orc.spins(L, 2, 9, 3)
+        S = S0.copy()
+        w = orc.new_walkers(1, orc.energy(L, J, S))
+        thr = np.full((K, 8), 2 ** 31, np.uint32)
+        seed, t, real, walker = 0xDEADBEEF12345678, 7, 9, 3
+        orc.muca_sweeps(L, J, S, w, thr, 0, -10 ** 6, 10 ** 6, seed, real, walker, t, 1)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        for i in range(N):
+            x, y, z = i % L, (i // L) % L, i // (L * L)
+            c = (x + y + z) % 2
+            q = sum(1 for yy in range(L) for xx in range(L) if (xx + yy + z) % 2 == c and xx + L * yy < x + L * y)
+            r = orc.philox([((c * L + z) << 8) | (q >> 2), t, real, (walker << 8) | orc.TAG_ACC], key)[q & 3]
+            assert (S[i] != S0[i]) == (int(r) < 2 ** 31)
