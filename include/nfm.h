@@ -120,7 +120,7 @@ int64_t nfm_n_walkers(const nfm_ctx* ctx);              /* total walkers of the 
 int32_t nfm_levels(const nfm_ctx* ctx, int32_t r);      /* K of realization r (after couplings) */
 int32_t nfm_e_base(const nfm_ctx* ctx, int32_t r);      /* e_base of realization r */
 int64_t nfm_level_offset(const nfm_ctx* ctx, int32_t r);/* start of r in histogram / level arrays */
-int64_t nfm_levels_total(const nfm_ctx* ctx);           /* sum of K over the batch */
+int64_t nfm_levels_total(const nfm_ctx* ctx);           /* length of histogram / level arrays */
 int64_t nfm_walker_offset(const nfm_ctx* ctx, int32_t r);/* global index of r's first walker */
 uint64_t nfm_sweep_counter(const nfm_ctx* ctx);         /* sweeps done so far */
 
@@ -151,8 +151,8 @@ nfm_status nfm_compute_energies(nfm_ctx* ctx);
 /* Tables. nfm_set_thresholds copies a raw table for realization r: rows x 8
  * uint32 (host) covering levels [row0, row0+rows); 1 <= rows <= K.
  * nfm_set_weights_lnw builds the tables of all realizations on the device from
- * log-weights: host lnw holds, for each realization, K doubles indexed by level
- * (only [k_lo[r], k_top[r]] is read); the table covers
+ * log-weights: host lnw holds nfm_levels_total() doubles, realization r's level k
+ * at index nfm_level_offset(r) + k (only [k_lo[r], k_top[r]] is read); the table covers
  * [max(0,k_lo-3), min(K-1,k_top+3)] with step log-weights d(j) = lnw(j+1)-lnw(j)
  * on [k_lo, k_top), d(j) = 0 for j >= k_top, d(j) = d(k_lo) for j < k_lo; entry
  * (k,u), m = 3-u: x = exp(d(k)+..+d(k+m-1)) (m>0), exp(-(d(k+m)+..+d(k-1))) (m<0),
@@ -177,8 +177,9 @@ nfm_status nfm_set_rt_bounds(nfm_ctx* ctx, int32_t r, int32_t e_bot, int32_t e_t
  * the last nfm_reset_trace). Sec. II, Eq. (2); Sec. III. */
 nfm_status nfm_run_sweeps(nfm_ctx* ctx, uint64_t n_sweeps);
 
-/* Histograms: sum over realizations of K uint64 (level order), accumulated since
- * the last reset. reset != 0 clears them after reading. */
+/* Histograms: nfm_levels_total() uint64; realization r's count of level k is at
+ * nfm_level_offset(r) + k (each realization reserves 3N/2+1 entries, K of them used).
+ * Counts accumulate since the last reset; reset != 0 clears them after reading. */
 nfm_status nfm_read_histograms(nfm_ctx* ctx, uint64_t* host_dst, int reset);
 nfm_status nfm_reset_histograms(nfm_ctx* ctx);
 nfm_status nfm_read_walkers(nfm_ctx* ctx, nfm_walker_stats* host_dst);   /* all walkers */

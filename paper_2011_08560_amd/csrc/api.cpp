@@ -1,0 +1,600 @@
+// C ABI of libnfm (include/nfm.h): context, workspace layout, argument checking and
+// kernel launches on the caller's stream. All device memory is the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nfm.h"
+#include "kernels.hpp"
+
+using nfm::RealInfo;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kMaxSweepsPerLaunch = 1024;
+constexpr int kNoBottom = -(1 << 20);  // far below any energy; keeps (k - row0) * 32 in int range
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t reals, waves, jabi, jk, spins, ws_i32, ws_u64, tables, hist, lnw, klo, ktop, trace, rstats, staging, total;
+  int64_t total_walkers, total_waves, levels_total, jabi_words, jk_words, spin_words, table_words;
+  size_t staging_bytes;
+};
+
+bool valid_L(int L) { return nfm::sweep_supported(L); }
+
+// Deterministic workspace layout of a batch (the same for nfm_workspace_bytes and nfm_create).
+bool make_layout(const nfm_batch_desc* d, Layout* lay, std::string* why) {
+  if (!d || d->n_real < 1 || !d->L || !d->walkers) {
+    *why = "batch description needs n_real >= 1 and L/walkers arrays";
+    return false;
+  }
+  if (d->trace_capacity < 0) {
+    *why = "trace_capacity must be >= 0";
+    return false;
+  }
+  Layout l{};
+  size_t max_stage = 0;
+  for (int r = 0; r < d->n_real; ++r) {
+    const int L = d->L[r], W = d->walkers[r];
+    if (!valid_L(L)) {
+      *why = "unsupported L (even, 2..12): realization " + std::to_string(r);
+      return false;
+    }
+    if (W < 64 || W % 64 != 0) {
+      *why = "walkers per realization must be a positive multiple of 64: realization " + std::to_string(r);
+      return false;
+    }
+    const int N = L * L * L;
+    l.total_walkers += W;
+    l.total_waves += W / 64;
+    l.levels_total += nfm::level_capacity(N);
+    l.jabi_words += 3 * nfm::abi_plane_words(N);
+    l.jk_words += nfm::jk_words(L);
+    l.spin_words += (int64_t)W * nfm::walker_words(L);
+    l.table_words += (int64_t)nfm::level_capacity(N) * 8;
+    max_stage = std::max(max_stage, (size_t)W * N);
+  }
+  max_stage = std::max(max_stage, (size_t)l.jabi_words * 4);
+  l.staging_bytes = max_stage;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  l.reals = take(sizeof(RealInfo) * d->n_real);
+  l.waves = take(sizeof(int32_t) * 2 * l.total_waves);
+  l.jabi = take(4 * (size_t)l.jabi_words);
+  l.jk = take(4 * (size_t)l.jk_words);
+  l.spins = take(4 * (size_t)l.spin_words);
+  l.ws_i32 = take(4 * 4 * (size_t)l.total_walkers);
+  l.ws_u64 = take(8 * 3 * (size_t)l.total_walkers);
+  l.tables = take(4 * (size_t)l.table_words);
+  l.hist = take(8 * (size_t)l.levels_total);
+  l.lnw = take(8 * (size_t)l.levels_total);
+  l.klo = take(4 * (size_t)d->n_real);
+  l.ktop = take(4 * (size_t)d->n_real);
+  l.trace = take(4 * (size_t)l.total_walkers * (size_t)d->trace_capacity);
+  l.rstats = take(sizeof(nfm::RealStatsDev) * d->n_real);
+  l.staging = take(l.staging_bytes);
+  l.total = off;
+  *lay = l;
+  return true;
+}
+
+}  // namespace
+
+struct nfm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout lay{};
+  int n_real = 0;
+  uint64_t disorder_seed = 0, walker_seed = 0;
+  int trace_cap = 0;
+  uint64_t sweeps = 0, trace_t0 = 0;
+  bool couplings = false;
+  std::vector<RealInfo> reals;
+  // waves grouped by L
+  std::vector<int> group_L;
+  std::vector<int64_t> group_first_wave, group_n_waves;
+  std::string err;
+
+  RealInfo* d_reals() { return (RealInfo*)(ws + lay.reals); }
+  int32_t* d_waves() { return (int32_t*)(ws + lay.waves); }
+  uint32_t* d_jabi() { return (uint32_t*)(ws + lay.jabi); }
+  uint32_t* d_jk() { return (uint32_t*)(ws + lay.jk); }
+  uint32_t* d_spins() { return (uint32_t*)(ws + lay.spins); }
+  uint32_t* d_tables() { return (uint32_t*)(ws + lay.tables); }
+  unsigned long long* d_hist() { return (unsigned long long*)(ws + lay.hist); }
+  double* d_lnw() { return (double*)(ws + lay.lnw); }
+  int32_t* d_klo() { return (int32_t*)(ws + lay.klo); }
+  int32_t* d_ktop() { return (int32_t*)(ws + lay.ktop); }
+  int32_t* d_trace() { return (int32_t*)(ws + lay.trace); }
+  nfm::RealStatsDev* d_rstats() { return (nfm::RealStatsDev*)(ws + lay.rstats); }
+  void* d_staging() { return ws + lay.staging; }
+  nfm::WalkerState walker_state() {
+    nfm::WalkerState s;
+    const int64_t W = lay.total_walkers;
+    int32_t* i32 = (int32_t*)(ws + lay.ws_i32);
+    uint64_t* u64 = (uint64_t*)(ws + lay.ws_u64);
+    s.E = i32;
+    s.E_min = i32 + W;
+    s.rt_state = i32 + 2 * W;
+    s.new_min = i32 + 3 * W;
+    s.rt_count = u64;
+    s.t_first = u64 + W;
+    s.t_last = u64 + 2 * W;
+    return s;
+  }
+};
+
+namespace {
+
+nfm_status fail(nfm_ctx* c, nfm_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define NFM_HIP(c, call)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail((c), NFM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define NFM_GUARD(c)                                   \
+  if (!(c)) return NFM_EINVAL;                         \
+  if (hipSetDevice((c)->device) != hipSuccess) return fail((c), NFM_EDEVICE, "hipSetDevice failed")
+
+#define NFM_TRY(c, ...)                                                          \
+  try {                                                                          \
+    __VA_ARGS__                                                                  \
+  } catch (const std::bad_alloc&) {                                              \
+    return fail((c), NFM_EDEVICE, "host allocation failed");                     \
+  } catch (...) {                                                                \
+    return fail((c), NFM_EDEVICE, "unexpected host exception");                  \
+  }
+
+nfm_status push_reals(nfm_ctx* c) {
+  NFM_HIP(c, hipMemcpyAsync(c->d_reals(), c->reals.data(), sizeof(RealInfo) * c->n_real, hipMemcpyHostToDevice,
+                            c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status pull_reals(nfm_ctx* c) {
+  NFM_HIP(c, hipMemcpyAsync(c->reals.data(), c->d_reals(), sizeof(RealInfo) * c->n_real, hipMemcpyDeviceToHost,
+                            c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+int max_walkers(const nfm_ctx* c) {
+  int m = 0;
+  for (const auto& r : c->reals) m = std::max(m, r.walkers);
+  return m;
+}
+
+// realization owning global walker index w
+int real_of_walker(const nfm_ctx* c, int64_t w) {
+  for (int r = 0; r < c->n_real; ++r)
+    if (w >= c->reals[r].walker_off && w < c->reals[r].walker_off + c->reals[r].walkers) return r;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+nfm_status nfm_workspace_bytes(const nfm_batch_desc* desc, size_t* bytes) {
+  if (!bytes) return NFM_EINVAL;
+  Layout l;
+  std::string why;
+  if (!make_layout(desc, &l, &why)) return NFM_EINVAL;
+  *bytes = l.total;
+  return NFM_OK;
+}
+
+nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_workspace, size_t workspace_bytes,
+                      int device, void* hip_stream) {
+  if (!out) return NFM_EINVAL;
+  *out = nullptr;
+  Layout l;
+  std::string why;
+  if (!make_layout(desc, &l, &why)) return NFM_EINVAL;
+  if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign) != 0) return NFM_EINVAL;
+  if (workspace_bytes < l.total) return NFM_ESIZE;
+  nfm_ctx* c = new (std::nothrow) nfm_ctx();
+  if (!c) return NFM_EDEVICE;
+  try {
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)dev_workspace;
+    c->lay = l;
+    c->n_real = desc->n_real;
+    c->disorder_seed = desc->disorder_seed;
+    c->walker_seed = desc->walker_seed;
+    c->trace_cap = desc->trace_capacity;
+    c->reals.resize(desc->n_real);
+    int64_t woff = 0, soff = 0, loff = 0, toff = 0, jaoff = 0, jkoff = 0;
+    for (int r = 0; r < desc->n_real; ++r) {
+      RealInfo& ri = c->reals[r];
+      std::memset(&ri, 0, sizeof(ri));
+      ri.L = desc->L[r];
+      ri.N = ri.L * ri.L * ri.L;
+      ri.e_base = -3 * ri.N;
+      ri.K = nfm::level_capacity(ri.N);
+      ri.walkers = desc->walkers[r];
+      ri.row0 = 0;
+      ri.rows = 0;
+      ri.e_bot = kNoBottom;
+      ri.e_top = 0;
+      ri.real_id = desc->first_real_id + (uint32_t)r;
+      ri.walker_off = woff;
+      ri.spin_off = soff;
+      ri.level_off = loff;
+      ri.table_off = toff;
+      ri.jabi_off = jaoff;
+      ri.jk_off = jkoff;
+      woff += ri.walkers;
+      soff += (int64_t)ri.walkers * nfm::walker_words(ri.L);
+      loff += nfm::level_capacity(ri.N);
+      toff += (int64_t)nfm::level_capacity(ri.N) * 8;
+      jaoff += 3 * nfm::abi_plane_words(ri.N);
+      jkoff += nfm::jk_words(ri.L);
+    }
+    // waves grouped by L (ascending), in realization order within a group
+    std::vector<int32_t> waves;
+    for (int L = 2; L <= nfm::kMaxL; L += 2) {
+      const int64_t first = (int64_t)waves.size() / 2;
+      for (int r = 0; r < desc->n_real; ++r) {
+        if (c->reals[r].L != L) continue;
+        for (int wl = 0; wl < c->reals[r].walkers; wl += 64) {
+          waves.push_back(r);
+          waves.push_back(wl);
+        }
+      }
+      const int64_t n = (int64_t)waves.size() / 2 - first;
+      if (n > 0) {
+        c->group_L.push_back(L);
+        c->group_first_wave.push_back(first);
+        c->group_n_waves.push_back(n);
+      }
+    }
+    // device arrays: wave_real[total_waves] then wave_wl[total_waves]
+    std::vector<int32_t> wr(l.total_waves), wwl(l.total_waves);
+    for (int64_t i = 0; i < l.total_waves; ++i) {
+      wr[i] = waves[2 * i];
+      wwl[i] = waves[2 * i + 1];
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return NFM_EDEVICE;
+    }
+    nfm_status st = NFM_OK;
+    if (hipMemcpyAsync(c->d_waves(), wr.data(), 4 * wr.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_waves() + l.total_waves, wwl.data(), 4 * wwl.size(), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ws + l.ws_i32, 0, 4 * 4 * (size_t)l.total_walkers, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ws + l.ws_u64, 0, 8 * 3 * (size_t)l.total_walkers, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ws + l.hist, 0, 8 * (size_t)l.levels_total, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ws + l.spins, 0, 4 * (size_t)l.spin_words, c->stream) != hipSuccess)
+      st = NFM_EDEVICE;
+    if (st == NFM_OK) st = push_reals(c);
+    if (st != NFM_OK) {
+      delete c;
+      return st;
+    }
+  } catch (...) {
+    delete c;
+    return NFM_EDEVICE;
+  }
+  *out = c;
+  return NFM_OK;
+}
+
+void nfm_destroy(nfm_ctx* ctx) {
+  if (!ctx) return;
+  if (hipSetDevice(ctx->device) == hipSuccess) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* nfm_last_error(const nfm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t nfm_n_real(const nfm_ctx* c) { return c ? c->n_real : 0; }
+int64_t nfm_n_walkers(const nfm_ctx* c) { return c ? c->lay.total_walkers : 0; }
+int32_t nfm_levels(const nfm_ctx* c, int32_t r) { return (c && r >= 0 && r < c->n_real) ? c->reals[r].K : 0; }
+int32_t nfm_e_base(const nfm_ctx* c, int32_t r) { return (c && r >= 0 && r < c->n_real) ? c->reals[r].e_base : 0; }
+int64_t nfm_level_offset(const nfm_ctx* c, int32_t r) {
+  return (c && r >= 0 && r < c->n_real) ? c->reals[r].level_off : -1;
+}
+int64_t nfm_levels_total(const nfm_ctx* c) { return c ? c->lay.levels_total : 0; }
+int64_t nfm_walker_offset(const nfm_ctx* c, int32_t r) {
+  return (c && r >= 0 && r < c->n_real) ? c->reals[r].walker_off : -1;
+}
+uint64_t nfm_sweep_counter(const nfm_ctx* c) { return c ? c->sweeps : 0; }
+
+static nfm_status after_couplings(nfm_ctx* c) {
+  hipError_t e = nfm::launch_pack_couplings(c->d_reals(), c->n_real, c->d_jabi(), c->d_jk(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("pack_couplings: ") + hipGetErrorString(e));
+  nfm_status s = pull_reals(c);
+  if (s != NFM_OK) return s;
+  for (auto& r : c->reals) {  // tables refer to the old level set
+    r.row0 = 0;
+    r.rows = 0;
+  }
+  c->couplings = true;
+  return push_reals(c);
+}
+
+nfm_status nfm_init_couplings(nfm_ctx* c) {
+  NFM_GUARD(c);
+  NFM_TRY(c, {
+    hipError_t e = nfm::launch_gen_couplings(c->d_reals(), c->n_real, c->d_jabi(), c->disorder_seed, c->stream);
+    if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("gen_couplings: ") + hipGetErrorString(e));
+    return after_couplings(c);
+  })
+}
+
+nfm_status nfm_set_couplings(nfm_ctx* c, int32_t r0, int32_t count, const uint32_t* host_words) {
+  NFM_GUARD(c);
+  if (!host_words || r0 < 0 || count < 1 || r0 + count > c->n_real)
+    return fail(c, NFM_EINVAL, "set_couplings: bad realization range or null pointer");
+  NFM_TRY(c, {
+    const int64_t first = c->reals[r0].jabi_off;
+    const int64_t last = c->reals[r0 + count - 1].jabi_off + 3 * nfm::abi_plane_words(c->reals[r0 + count - 1].N);
+    NFM_HIP(c, hipMemcpyAsync(c->d_jabi() + first, host_words, 4 * (size_t)(last - first), hipMemcpyHostToDevice,
+                              c->stream));
+    return after_couplings(c);
+  })
+}
+
+nfm_status nfm_get_couplings(nfm_ctx* c, int32_t r0, int32_t count, uint32_t* host_words) {
+  NFM_GUARD(c);
+  if (!host_words || r0 < 0 || count < 1 || r0 + count > c->n_real)
+    return fail(c, NFM_EINVAL, "get_couplings: bad realization range or null pointer");
+  const int64_t first = c->reals[r0].jabi_off;
+  const int64_t last = c->reals[r0 + count - 1].jabi_off + 3 * nfm::abi_plane_words(c->reals[r0 + count - 1].N);
+  NFM_HIP(c, hipMemcpyAsync(host_words, c->d_jabi() + first, 4 * (size_t)(last - first), hipMemcpyDeviceToHost,
+                            c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_init_spins(nfm_ctx* c) {
+  NFM_GUARD(c);
+  hipError_t e = nfm::launch_gen_spins(c->d_reals(), 0, c->n_real, max_walkers(c), c->d_spins(), c->walker_seed,
+                                       c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("gen_spins: ") + hipGetErrorString(e));
+  return NFM_OK;
+}
+
+static nfm_status spins_io(nfm_ctx* c, int64_t w0, int64_t count, const int8_t* src, int8_t* dst) {
+  if ((!src && !dst) || w0 < 0 || count < 1 || w0 + count > c->lay.total_walkers)
+    return fail(c, NFM_EINVAL, "spins: bad walker range or null pointer");
+  NFM_TRY(c, {
+    int64_t w = w0, done = 0;
+    while (done < count) {
+      const int r = real_of_walker(c, w);
+      const RealInfo& ri = c->reals[r];
+      const int64_t wl0 = w - ri.walker_off;
+      const int64_t n = std::min<int64_t>(count - done, ri.walkers - wl0);
+      const size_t bytes = (size_t)n * ri.N;
+      int8_t* stage = (int8_t*)c->d_staging();
+      if (src) {
+        NFM_HIP(c, hipMemcpyAsync(stage, src + done * ri.N, bytes, hipMemcpyHostToDevice, c->stream));
+        hipError_t e = nfm::launch_pack_spins(c->d_reals(), r, (int)wl0, (int)n, stage, c->d_spins(), c->stream);
+        if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("pack_spins: ") + hipGetErrorString(e));
+        NFM_HIP(c, hipStreamSynchronize(c->stream));
+      } else {
+        hipError_t e = nfm::launch_unpack_spins(c->d_reals(), r, (int)wl0, (int)n, c->d_spins(), stage, c->stream);
+        if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("unpack_spins: ") + hipGetErrorString(e));
+        NFM_HIP(c, hipMemcpyAsync(dst + done * ri.N, stage, bytes, hipMemcpyDeviceToHost, c->stream));
+        NFM_HIP(c, hipStreamSynchronize(c->stream));
+      }
+      done += n;
+      w += n;
+    }
+    return NFM_OK;
+  })
+}
+
+nfm_status nfm_set_spins(nfm_ctx* c, int64_t w0, int64_t count, const int8_t* host_spins) {
+  NFM_GUARD(c);
+  if (!host_spins) return fail(c, NFM_EINVAL, "set_spins: null pointer");
+  return spins_io(c, w0, count, host_spins, nullptr);
+}
+
+nfm_status nfm_get_spins(nfm_ctx* c, int64_t w0, int64_t count, int8_t* host_spins) {
+  NFM_GUARD(c);
+  if (!host_spins) return fail(c, NFM_EINVAL, "get_spins: null pointer");
+  return spins_io(c, w0, count, nullptr, host_spins);
+}
+
+nfm_status nfm_compute_energies(nfm_ctx* c) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "compute_energies: couplings not set");
+  hipError_t e = nfm::launch_energy(c->d_reals(), c->n_real, max_walkers(c), c->d_jabi(), c->d_spins(),
+                                    c->walker_state(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("energy: ") + hipGetErrorString(e));
+  return NFM_OK;
+}
+
+nfm_status nfm_set_thresholds(nfm_ctx* c, int32_t r, const uint32_t* host_thr, int32_t row0, int32_t rows) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "set_thresholds: couplings not set");
+  if (!host_thr || r < 0 || r >= c->n_real) return fail(c, NFM_EINVAL, "set_thresholds: bad realization");
+  RealInfo& ri = c->reals[r];
+  if (rows < 1 || row0 < 0 || row0 + rows > ri.K) return fail(c, NFM_EINVAL, "set_thresholds: rows outside [0, K)");
+  NFM_HIP(c, hipMemcpyAsync(c->d_tables() + ri.table_off, host_thr, 4 * 8 * (size_t)rows, hipMemcpyHostToDevice,
+                            c->stream));
+  ri.row0 = row0;
+  ri.rows = rows;
+  return push_reals(c);
+}
+
+nfm_status nfm_get_thresholds(nfm_ctx* c, int32_t r, uint32_t* host_thr, int32_t* row0, int32_t* rows) {
+  NFM_GUARD(c);
+  if (r < 0 || r >= c->n_real || !row0 || !rows) return fail(c, NFM_EINVAL, "get_thresholds: bad arguments");
+  const RealInfo& ri = c->reals[r];
+  *row0 = ri.row0;
+  *rows = ri.rows;
+  if (host_thr && ri.rows > 0) {
+    NFM_HIP(c, hipMemcpyAsync(host_thr, c->d_tables() + ri.table_off, 4 * 8 * (size_t)ri.rows, hipMemcpyDeviceToHost,
+                              c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return NFM_OK;
+}
+
+nfm_status nfm_set_weights_lnw(nfm_ctx* c, const double* host_lnw, const int32_t* k_lo, const int32_t* k_top) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "set_weights_lnw: couplings not set");
+  if (!host_lnw || !k_lo || !k_top) return fail(c, NFM_EINVAL, "set_weights_lnw: null pointer");
+  for (int r = 0; r < c->n_real; ++r)
+    if (k_lo[r] < 0 || k_top[r] >= c->reals[r].K || k_lo[r] > k_top[r])
+      return fail(c, NFM_EINVAL, "set_weights_lnw: need 0 <= k_lo <= k_top < K, realization " + std::to_string(r));
+  NFM_HIP(c, hipMemcpyAsync(c->d_lnw(), host_lnw, 8 * (size_t)c->lay.levels_total, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(c->d_klo(), k_lo, 4 * (size_t)c->n_real, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(c->d_ktop(), k_top, 4 * (size_t)c->n_real, hipMemcpyHostToDevice, c->stream));
+  hipError_t e = nfm::launch_build_tables(c->d_reals(), c->n_real, c->d_lnw(), c->d_klo(), c->d_ktop(),
+                                          c->d_tables(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("build_tables: ") + hipGetErrorString(e));
+  return pull_reals(c);
+}
+
+nfm_status nfm_set_rt_bounds(nfm_ctx* c, int32_t r, int32_t e_bot, int32_t e_top) {
+  NFM_GUARD(c);
+  if (r < 0 || r >= c->n_real) return fail(c, NFM_EINVAL, "set_rt_bounds: bad realization");
+  const int N = c->reals[r].N;
+  if (e_bot < -4 * N || e_bot > 4 * N || e_top < -4 * N || e_top > 4 * N)
+    return fail(c, NFM_EINVAL, "set_rt_bounds: bounds outside [-4N, 4N]");
+  c->reals[r].e_bot = e_bot;
+  c->reals[r].e_top = e_top;
+  return push_reals(c);
+}
+
+nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "run_sweeps: couplings not set");
+  for (int r = 0; r < c->n_real; ++r)
+    if (c->reals[r].rows < 1) return fail(c, NFM_ESTATE, "run_sweeps: no threshold table, realization " + std::to_string(r));
+  if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
+    return fail(c, NFM_ERANGE, "run_sweeps: the sweep counter must stay below 2^32");
+  uint64_t done = 0;
+  while (done < n_sweeps) {
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(kMaxSweepsPerLaunch, n_sweeps - done);
+    for (size_t g = 0; g < c->group_L.size(); ++g) {
+      const int L = c->group_L[g];
+      int lds_rows = 1;
+      for (const auto& ri : c->reals)
+        if (ri.L == L) lds_rows = std::max(lds_rows, ri.rows);
+      nfm::SweepArgs a{};
+      a.reals = c->d_reals();
+      a.wave_real = c->d_waves() + c->group_first_wave[g];
+      a.wave_wl = c->d_waves() + c->lay.total_waves + c->group_first_wave[g];
+      a.spins = c->d_spins();
+      a.jk = c->d_jk();
+      a.tables = c->d_tables();
+      a.ws = c->walker_state();
+      a.hist = c->d_hist();
+      a.trace = c->d_trace();
+      a.trace_cap = c->trace_cap;
+      a.trace_t0 = c->trace_t0;
+      a.t0 = c->sweeps + done;
+      a.n_sweeps = chunk;
+      a.walker_seed = c->walker_seed;
+      hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, c->stream);
+      if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
+    }
+    done += chunk;
+  }
+  c->sweeps += n_sweeps;
+  return NFM_OK;
+}
+
+nfm_status nfm_read_histograms(nfm_ctx* c, uint64_t* host_dst, int reset) {
+  NFM_GUARD(c);
+  if (!host_dst) return fail(c, NFM_EINVAL, "read_histograms: null pointer");
+  NFM_HIP(c, hipMemcpyAsync(host_dst, c->d_hist(), 8 * (size_t)c->lay.levels_total, hipMemcpyDeviceToHost, c->stream));
+  if (reset) NFM_HIP(c, hipMemsetAsync(c->d_hist(), 0, 8 * (size_t)c->lay.levels_total, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_reset_histograms(nfm_ctx* c) {
+  NFM_GUARD(c);
+  NFM_HIP(c, hipMemsetAsync(c->d_hist(), 0, 8 * (size_t)c->lay.levels_total, c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_read_walkers(nfm_ctx* c, nfm_walker_stats* host_dst) {
+  NFM_GUARD(c);
+  if (!host_dst) return fail(c, NFM_EINVAL, "read_walkers: null pointer");
+  NFM_TRY(c, {
+    const int64_t W = c->lay.total_walkers;
+    std::vector<int32_t> i32(4 * W);
+    std::vector<uint64_t> u64(3 * W);
+    NFM_HIP(c, hipMemcpyAsync(i32.data(), c->ws + c->lay.ws_i32, 4 * i32.size(), hipMemcpyDeviceToHost, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(u64.data(), c->ws + c->lay.ws_u64, 8 * u64.size(), hipMemcpyDeviceToHost, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    for (int64_t w = 0; w < W; ++w) {
+      host_dst[w].E = i32[w];
+      host_dst[w].E_min = i32[W + w];
+      host_dst[w].rt_state = i32[2 * W + w];
+      host_dst[w].new_min = i32[3 * W + w];
+      host_dst[w].rt_count = u64[w];
+      host_dst[w].t_first = u64[W + w];
+      host_dst[w].t_last = u64[2 * W + w];
+    }
+    return NFM_OK;
+  })
+}
+
+nfm_status nfm_read_realizations(nfm_ctx* c, nfm_real_stats* host_dst) {
+  NFM_GUARD(c);
+  if (!host_dst) return fail(c, NFM_EINVAL, "read_realizations: null pointer");
+  static_assert(sizeof(nfm_real_stats) == sizeof(nfm::RealStatsDev), "layout");
+  hipError_t e = nfm::launch_reduce_real(c->d_reals(), c->n_real, c->walker_state(), c->d_rstats(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("reduce_real: ") + hipGetErrorString(e));
+  NFM_HIP(c, hipMemcpyAsync(host_dst, c->d_rstats(), sizeof(nfm_real_stats) * c->n_real, hipMemcpyDeviceToHost,
+                            c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_read_trace(nfm_ctx* c, int32_t* host_dst, int32_t* n_valid) {
+  NFM_GUARD(c);
+  if (!n_valid) return fail(c, NFM_EINVAL, "read_trace: null pointer");
+  const uint64_t done = c->sweeps - c->trace_t0;
+  *n_valid = (int32_t)std::min<uint64_t>(done, (uint64_t)c->trace_cap);
+  if (c->trace_cap > 0) {
+    if (!host_dst) return fail(c, NFM_EINVAL, "read_trace: null pointer");
+    NFM_HIP(c, hipMemcpyAsync(host_dst, c->d_trace(), 4 * (size_t)c->lay.total_walkers * c->trace_cap,
+                              hipMemcpyDeviceToHost, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return NFM_OK;
+}
+
+nfm_status nfm_reset_trace(nfm_ctx* c) {
+  NFM_GUARD(c);
+  c->trace_t0 = c->sweeps;
+  return NFM_OK;
+}
+
+nfm_status nfm_sync(nfm_ctx* c) {
+  NFM_GUARD(c);
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Host-side launchers of the libnfm kernels (one HIP source file per group).
+#pragma once
+#include "nfm_internal.hpp"
+
+namespace nfm {
+
+struct RealStatsDev {        // same layout as nfm_real_stats
+  uint64_t rt_count;
+  uint64_t rt_time;
+  int32_t E_min;
+  int32_t new_min;
+  int32_t walkers_with_trips;
+  int32_t pad;
+  uint64_t reserved;
+};
+
+// lattice.hip
+hipError_t launch_gen_couplings(const RealInfo* reals, int n_real, uint32_t* jabi, uint64_t seed, hipStream_t s);
+hipError_t launch_pack_couplings(RealInfo* reals, int n_real, const uint32_t* jabi, uint32_t* jk, hipStream_t s);
+hipError_t launch_gen_spins(const RealInfo* reals, int r0, int nr, int max_walkers, uint32_t* spins, uint64_t seed,
+                            hipStream_t s);
+hipError_t launch_pack_spins(const RealInfo* reals, int r, int wl0, int count, const int8_t* src, uint32_t* spins,
+                             hipStream_t s);
+hipError_t launch_unpack_spins(const RealInfo* reals, int r, int wl0, int count, const uint32_t* spins, int8_t* dst,
+                               hipStream_t s);
+hipError_t launch_energy(const RealInfo* reals, int n_real, int max_walkers, const uint32_t* jabi,
+                         const uint32_t* spins, WalkerState ws, hipStream_t s);
+hipError_t launch_reduce_real(const RealInfo* reals, int n_real, WalkerState ws, RealStatsDev* out, hipStream_t s);
+
+// tables.hip
+hipError_t launch_build_tables(RealInfo* reals, int n_real, const double* lnw, const int32_t* k_lo,
+                               const int32_t* k_top, uint32_t* tables, hipStream_t s);
+
+// sweep.hip
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s);
+bool sweep_supported(int L);
+
+}  // namespace nfm

@@ -1,0 +1,74 @@
+// Internal definitions of libnfm shared by the host API and the kernels.
+// Geometry of the kernel's spin layout, per-realization records and kernel
+// argument blocks. Model and conventions: see include/nfm.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace nfm {
+
+constexpr int kMaxL = 12;
+constexpr int kWave = 64;
+constexpr uint32_t kTagAcc = 1, kTagSpin = 2, kTagJ = 3;
+
+// Kernel spin layout. A walker's lattice is split by colour c = (x+y+z)&1 and
+// plane z; the L/2 sites of colour c in row y of plane z (x = 2j + phi,
+// phi = (c+y+z)&1) sit in bits j of a field of F bits at offset y*F of the
+// plane-colour bit string, which occupies NWP 32-bit words.
+__host__ __device__ constexpr int field_bits(int L) { return L <= 2 ? 1 : L <= 4 ? 2 : L <= 8 ? 4 : 8; }
+__host__ __device__ constexpr int plane_words(int L) { return (L * field_bits(L) + 31) / 32; }
+__host__ __device__ constexpr int walker_words(int L) { return 2 * L * plane_words(L); }
+// Kernel coupling layout per realization: for every (c, z) six bit strings in
+// the same field layout: [Jz fwd, Jz bwd, Jy fwd, Jy bwd, Jx partner, Jx other].
+__host__ __device__ constexpr int jk_words(int L) { return 2 * L * 6 * plane_words(L); }
+__host__ __device__ constexpr int abi_plane_words(int N) { return (N + 31) / 32; }
+__host__ __device__ constexpr int level_capacity(int N) { return 3 * N / 2 + 1; }
+
+// Per-realization record (device and host mirror).
+struct RealInfo {
+  int32_t L, N, K, e_base;
+  int32_t walkers, n_minus;
+  int32_t row0, rows;        // current threshold table covers levels [row0, row0+rows)
+  int32_t e_bot, e_top;      // round-trip bounds
+  uint32_t real_id;
+  int32_t pad;
+  int64_t walker_off;        // global index of the first walker
+  int64_t spin_off;          // word offset into the spin buffer
+  int64_t level_off;         // offset into per-level arrays (capacity level_capacity(N))
+  int64_t table_off;         // word offset into the table buffer (capacity * 8 words)
+  int64_t jabi_off;          // word offset of the ABI couplings (3 * JW words)
+  int64_t jk_off;            // word offset of the kernel-layout couplings
+};
+
+struct WalkerState {         // structure of arrays over all walkers
+  int32_t* E;
+  int32_t* E_min;
+  int32_t* rt_state;
+  int32_t* new_min;
+  uint64_t* rt_count;
+  uint64_t* t_first;
+  uint64_t* t_last;
+};
+
+struct SweepArgs {
+  const RealInfo* reals;
+  const int32_t* wave_real;  // per wave of this launch: realization index
+  const int32_t* wave_wl;    // per wave: local index of its first walker
+  uint32_t* spins;
+  const uint32_t* jk;
+  const uint32_t* tables;
+  WalkerState ws;
+  unsigned long long* hist;
+  int32_t* trace;
+  int32_t trace_cap;
+  int32_t pad;
+  uint64_t trace_t0;         // first traced sweep
+  uint64_t t0;               // first sweep of this launch
+  uint32_t n_sweeps;
+  uint32_t pad2;
+  uint64_t walker_seed;
+};
+
+}  // namespace nfm

@@ -1,0 +1,347 @@
+// Multicanonical Metropolis sweeps (Sec. II, Eq. (2)) with per-attempt minimum and
+// round-trip bookkeeping (Sec. III) and per-sweep histograms.
+//
+// Mapping: one lane = one walker; one wave = 64 walkers of one realization, which
+// share its couplings (wave-uniform, scalar registers) and its threshold table
+// (LDS). A walker's lattice stays in VGPRs for the whole launch, bit-packed by
+// colour and plane (see nfm_internal.hpp).
+//
+// The sweep order is checkerboard: all sites of colour 0, then colour 1. The
+// neighbours of a site all have the other colour, so at the start of each
+// (colour, plane) block the number u of unsatisfied bonds of every site of the
+// block is fixed; it is computed for the whole block at once with word-parallel
+// bit operations (six flag strings and a bit-sliced adder). The attempts then run
+// one after the other, since each acceptance reads the walker's current energy.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace nfm {
+
+template <int L>
+struct Geo {
+  static constexpr int F = field_bits(L);
+  static constexpr int NWP = plane_words(L);
+  static constexpr int H = L / 2;           // sites of one colour per row
+  static constexpr int Q = L * L / 2;       // sites of one colour per plane
+  static constexpr int N = L * L * L;
+  static constexpr int BITS = L * F;
+  using PW = typename std::conditional<(BITS <= 32), uint32_t, __uint128_t>::type;
+
+  // bits [lo, lo+width) of every field
+  static constexpr PW fields(int lo, int width) {
+    PW m = 0;
+    for (int y = 0; y < L; ++y)
+      for (int b = lo; b < lo + width; ++b) m |= PW(1) << (y * F + b);
+    return m;
+  }
+  // valid bits of the rows y with y % 2 == parity
+  static constexpr PW rows_of_parity(int parity) {
+    PW m = 0;
+    for (int y = parity; y < L; y += 2)
+      for (int b = 0; b < H; ++b) m |= PW(1) << (y * F + b);
+    return m;
+  }
+  static constexpr PW all_bits() {
+    PW m = 0;
+    for (int b = 0; b < BITS; ++b) m |= PW(1) << b;
+    return m;
+  }
+};
+
+template <int L>
+__device__ __forceinline__ typename Geo<L>::PW pack(const uint32_t* w) {
+  using G = Geo<L>;
+  typename G::PW v = 0;
+#pragma unroll
+  for (int i = 0; i < G::NWP; ++i) v |= typename G::PW(w[i]) << (32 * i);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ void unpack(typename Geo<L>::PW v, uint32_t* w) {
+  using G = Geo<L>;
+#pragma unroll
+  for (int i = 0; i < G::NWP; ++i) w[i] = (uint32_t)(v >> (32 * i));
+}
+
+__device__ __forceinline__ int floor_div4(int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); }
+__device__ __forceinline__ int ceil_div4(int a) { return -floor_div4(-a); }
+
+// Bookkeeping window: while lo <= B <= hi an attempt cannot change the minimum, the
+// new-minimum flag or the round-trip state, so the exact update of Sec. III runs only for
+// groups of attempts in which B left the window. B = (k - row0) * 32 for level k.
+struct Window {
+  int lo, hi;
+};
+
+__device__ __forceinline__ Window make_window(int Bmin, int state, int newmin, int Bbot, int Btop, int Bnm) {
+  constexpr int INF = 1 << 29;
+  int lo = Bmin;
+  if (state == 1) lo = max(lo, Bbot + 32);
+  if (!newmin) lo = max(lo, Bnm + 32);
+  Window w;
+  w.lo = lo;
+  w.hi = (state != 1) ? Btop - 32 : INF;  // lo > hi: every attempt is examined
+  return w;
+}
+
+// Exact bookkeeping of one attempt (Sec. III): minimum, new-minimum flag, round trips.
+struct Track {
+  int Bmin, state, newmin;
+  uint32_t trips;
+  uint64_t t_first, t_last;
+};
+
+__device__ __forceinline__ void track_attempt(Track& tr, int B, uint64_t tau, int e_base, int row0, int e_bot,
+                                              int e_top) {
+  const int E = e_base + 4 * ((B >> 5) + row0);
+  if (B < tr.Bmin) tr.Bmin = B;
+  if (E < e_bot) tr.newmin = 1;
+  if (E >= e_top) {
+    if (tr.state == 2) {
+      tr.trips += 1;
+      tr.t_last = tau;
+    }
+    if (tr.state == 0) tr.t_first = tau;
+    tr.state = 1;
+  } else if (E <= e_bot && tr.state == 1) {
+    tr.state = 2;
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
+  using G = Geo<L>;
+  using PW = typename G::PW;
+  constexpr int NWP = G::NWP, Q = G::Q, N = G::N;
+  constexpr int NB = (G::BITS + 7) / 8;  // bytes of a plane-colour string
+  constexpr int kZUnroll = L <= 4 ? L : 1;
+  extern __shared__ uint32_t stab[];
+
+  const int r = A.wave_real[blockIdx.x];
+  const int wl = A.wave_wl[blockIdx.x] + (int)threadIdx.x;
+  const RealInfo& RI = A.reals[r];
+  const int row0 = RI.row0, rows = RI.rows, e_base = RI.e_base, walkers = RI.walkers;
+  const int e_bot = RI.e_bot, e_top = RI.e_top;
+  const uint32_t real_id = RI.real_id;
+  const int64_t gw = RI.walker_off + wl;
+
+  // threshold table -> LDS, each row permuted from u-order to m-order: LDS entry j holds
+  // the threshold of the step m = j (j < 4) or m = j - 8 (j > 4), i.e. of u = 3 - m.
+  // The dynamic LDS block is the kernel's only LDS, so it starts at address 0.
+  {
+    (void)stab;
+    const uint32_t* gt = A.tables + RI.table_off;
+    for (int e = threadIdx.x; e < rows * 8; e += 64) {
+      const int jj = e & 7;
+      const int u = jj < 4 ? 3 - jj : (jj == 4 ? 7 : 11 - jj);
+      *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = gt[(e & ~7) + u];
+    }
+  }
+  __syncthreads();
+
+  // walker state -> registers. One array per (colour, word) so that each stays small
+  // enough to live in VGPRs under a dynamic plane index.
+  uint32_t a00[L], a01[L], a02[L], a10[L], a11[L], a12[L];
+  auto lat = [&](int c, int w) -> uint32_t* {
+    return c == 0 ? (w == 0 ? a00 : w == 1 ? a01 : a02) : (w == 0 ? a10 : w == 1 ? a11 : a12);
+  };
+  static_assert(NWP <= 3, "plane-colour strings of at most 3 words");
+  {
+    const uint32_t* sp = A.spins + RI.spin_off + wl;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int w = 0; w < NWP; ++w)
+#pragma unroll
+        for (int z = 0; z < L; ++z) lat(c, w)[z] = sp[(int64_t)((c * L + z) * NWP + w) * walkers];
+  }
+  const int E0 = A.ws.E[gw];
+  int B = ((E0 - e_base) / 4 - row0) * 32;
+  Track tr;
+  tr.Bmin = ((A.ws.E_min[gw] - e_base) / 4 - row0) * 32;
+  tr.state = A.ws.rt_state[gw];
+  tr.newmin = A.ws.new_min[gw];
+  tr.trips = 0;
+  tr.t_first = A.ws.t_first[gw];
+  tr.t_last = A.ws.t_last[gw];
+
+  const int Bmax = (rows - 1) * 32;
+  const int Btop = (ceil_div4(e_top - e_base) - row0) * 32;    // E >= e_top  <=> B >= Btop
+  const int Bbot = (floor_div4(e_bot - e_base) - row0) * 32;   // E <= e_bot  <=> B <= Bbot
+  const int Bnm = (ceil_div4(e_bot - e_base) - 1 - row0) * 32; // E <  e_bot  <=> B <= Bnm
+  Window win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+
+  const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
+  const uint32_t ctr3 = ((uint32_t)wl << 8) | kTagAcc;
+  const uint32_t* jreal = A.jk + RI.jk_off;
+
+  for (uint32_t s = 0; s < A.n_sweeps; ++s) {
+    const uint64_t t = A.t0 + s;
+    const uint64_t tau0 = t * (uint64_t)N + 1u;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      // small lattices: planes unrolled (static register indices); larger ones: a plane loop
+      // whose dynamic index selects registers of the per-(colour, word) arrays
+#pragma unroll kZUnroll
+      for (int z = 0; z < L; ++z) {
+        const int zp = (z + 1 == L) ? 0 : z + 1;
+        const int zm = (z == 0) ? L - 1 : z - 1;
+        uint32_t Cw[NWP], Ow[NWP], Pw[NWP], Mw[NWP];
+#pragma unroll
+        for (int w = 0; w < NWP; ++w) {
+          Cw[w] = lat(c, w)[z];
+          Ow[w] = lat(1 - c, w)[z];
+          Pw[w] = lat(1 - c, w)[zp];
+          Mw[w] = lat(1 - c, w)[zm];
+        }
+        const uint32_t* jz = jreal + (c * L + z) * 6 * NWP;
+        uint32_t Jw[6][NWP];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+          for (int w = 0; w < NWP; ++w) Jw[k][w] = jz[k * NWP + w];
+
+        // flags: bit set <=> bond unsatisfied (S_i xor S_j xor [J = -1])
+        const PW own = pack<L>(Cw), O = pack<L>(Ow), Zp = pack<L>(Pw), Zm = pack<L>(Mw);
+        constexpr PW ALL = G::all_bits();
+        const PW Yp = ((O >> G::F) | (O << (G::F * (L - 1)))) & ALL;
+        const PW Ym = ((O << G::F) | (O >> (G::F * (L - 1)))) & ALL;
+        const PW Xm1 = ((O << 1) & G::fields(1, G::H - 1)) | ((O >> (G::H - 1)) & G::fields(0, 1));
+        const PW Xp1 = ((O >> 1) & G::fields(0, G::H - 1)) | ((O << (G::H - 1)) & G::fields(G::H - 1, 1));
+        // rows whose sites have odd x (phi = 1) take their "other" x-neighbour at j+1
+        const PW PHI = ((c + z) & 1) ? G::rows_of_parity(0) : G::rows_of_parity(1);
+        const PW Xo = (Xp1 & PHI) | (Xm1 & ~PHI);
+        const PW f1 = own ^ Zp ^ pack<L>(Jw[0]);
+        const PW f2 = own ^ Zm ^ pack<L>(Jw[1]);
+        const PW f3 = own ^ Yp ^ pack<L>(Jw[2]);
+        const PW f4 = own ^ Ym ^ pack<L>(Jw[3]);
+        const PW f5 = own ^ O ^ pack<L>(Jw[4]);
+        const PW f6 = own ^ Xo ^ pack<L>(Jw[5]);
+        // Bit-sliced u = f1 + ... + f6, delivered as the level step m = 3 - u in 3-bit two's
+        // complement: m = (7 - u) ^ 4, i.e. bits (~u0, ~u1, u2).
+        const PW s1 = f1 ^ f2 ^ f3, k1 = (f1 & f2) | (f3 & (f1 ^ f2));
+        const PW s2 = f4 ^ f5 ^ f6, k2 = (f4 & f5) | (f6 & (f4 ^ f5));
+        const PW t0 = s1 & s2;
+        uint32_t m0[NWP], m1[NWP], m2[NWP];
+        unpack<L>(~(s1 ^ s2), m0);
+        unpack<L>(~(k1 ^ k2 ^ t0), m1);
+        unpack<L>((k1 & k2) | (t0 & (k1 ^ k2)), m2);
+        // Byte-interleave: V[g8] = (0, m0.byte, m1.byte, m2.byte). For the site at bit b of
+        // that byte, (V & (0x01010100 << b)) * (2^(26-b) + 2^(19-b) + 2^(12-b)) puts its three
+        // bits at 2^34, 2^35, 2^36 and every other partial product at another single bit
+        // (no carries), so bits 2..4 of the high word are m & 7.
+        uint32_t V[NB];
+#pragma unroll
+        for (int g8 = 0; g8 < NB; ++g8) {
+          const int w = g8 >> 2;
+          const uint32_t bsel = (uint32_t)(g8 & 3);
+          // perm selector bytes: 0x0c -> 0x00; 0..3 pick src1 bytes, 4..7 pick src0 bytes
+          const uint32_t lo = __builtin_amdgcn_perm(m1[w], m0[w], 0x0c00000cu | (bsel << 8) | ((4u + bsel) << 16));
+          V[g8] = __builtin_amdgcn_perm(m2[w], lo, 0x00020100u | ((4u + bsel) << 24));
+          asm volatile("" : "+v"(V[g8]));
+        }
+
+        const uint32_t ctr0 = (uint32_t)(c * L + z) << 8;
+        const uint64_t tau_blk = tau0 + (uint64_t)(c * (N / 2) + z * Q);
+#pragma unroll
+        for (int g = 0; g < (Q + 3) / 4; ++g) {
+          const u32x4 rnd = philox4x32_10(ctr0 | (uint32_t)g, (uint32_t)t, real_id, ctr3, key0, key1);
+          int Bq[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int q = 4 * g + i;
+            Bq[i] = B;
+            if (q >= Q) continue;
+            const int y = q / G::H, j = q % G::H;
+            const int p = y * G::F + j, w = p >> 5, b = p & 31, g8 = p >> 3, bb = p & 7;
+            uint32_t cmul;  // per-site constant kept out of loop-invariant hoisting
+            asm volatile("s_mov_b32 %0, %1" : "=s"(cmul) : "i"((1u << (26 - bb)) + (1u << (19 - bb)) + (1u << (12 - bb))));
+            const uint32_t hi = __umulhi(V[g8] & (0x01010100u << bb), cmul);
+            int R;
+            asm("v_med3_i32 %0, %1, 0, %2" : "=v"(R) : "v"(B), "s"(Bmax));
+            const uint32_t addr = (hi & 0x1cu) | (uint32_t)R;      // R is a multiple of 32
+            const uint32_t th = *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr;
+            const uint32_t rv = min(rnd.v[i], 0xFFFFFFFEu);
+            if (rv < th) {
+              Cw[w] ^= 1u << b;
+              B += __builtin_amdgcn_sbfe((int)hi, 2, 3) * 32;             // 32 m
+            }
+            Bq[i] = B;
+          }
+          // Did any attempt of the group leave the window? Then replay the group exactly.
+          const int bmin = min(min(Bq[0], Bq[1]), min(Bq[2], Bq[3]));
+          const int bmax = max(max(Bq[0], Bq[1]), max(Bq[2], Bq[3]));
+          if (bmin < win.lo || bmax > win.hi) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int q = 4 * g + i;
+              if (q < Q) track_attempt(tr, Bq[i], tau_blk + (uint64_t)q, e_base, row0, e_bot, e_top);
+            }
+            win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+          }
+        }
+#pragma unroll
+        for (int w = 0; w < NWP; ++w) lat(c, w)[z] = Cw[w];
+      }
+    }
+    // end of sweep: histogram and trace
+    const int k = (B >> 5) + row0;
+    if (k >= 0 && k < RI.K) atomicAdd(A.hist + RI.level_off + k, 1ULL);  // always true for exact energies
+    if (t - A.trace_t0 < (uint64_t)A.trace_cap)
+      A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
+  }
+
+  // registers -> walker state
+  {
+    uint32_t* sp = A.spins + RI.spin_off + wl;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int w = 0; w < NWP; ++w)
+#pragma unroll
+        for (int z = 0; z < L; ++z) sp[(int64_t)((c * L + z) * NWP + w) * walkers] = lat(c, w)[z];
+  }
+  A.ws.E[gw] = e_base + 4 * ((B >> 5) + row0);
+  A.ws.E_min[gw] = e_base + 4 * ((tr.Bmin >> 5) + row0);
+  A.ws.rt_state[gw] = tr.state;
+  A.ws.new_min[gw] = tr.newmin;
+  A.ws.rt_count[gw] += tr.trips;
+  A.ws.t_first[gw] = tr.t_first;
+  A.ws.t_last[gw] = tr.t_last;
+}
+
+template <int L>
+static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s) {
+  // The kernel addresses its dynamic LDS block from address 0, which is only valid
+  // when the compiler placed nothing else in LDS.
+  static int checked = 0;
+  if (!checked) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_muca_sweeps<L>));
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+    checked = 1;
+  }
+  const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_muca_sweeps<L>, dim3(n_waves), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
+
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s) {
+  switch (L) {
+    case 2: return launch_L<2>(a, n_waves, lds_rows, s);
+    case 4: return launch_L<4>(a, n_waves, lds_rows, s);
+    case 6: return launch_L<6>(a, n_waves, lds_rows, s);
+    case 8: return launch_L<8>(a, n_waves, lds_rows, s);
+    case 10: return launch_L<10>(a, n_waves, lds_rows, s);
+    case 12: return launch_L<12>(a, n_waves, lds_rows, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace nfm

@@ -1,0 +1,305 @@
+"""Python binding of libnfm (include/nfm.h): argument marshalling only.
+
+Every step of the sampler runs in the HIP kernels of ``libnfm.so``. PyTorch is
+used for the device workspace and the stream. The binding refuses to run when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnfm.so")
+
+NFM_OK, NFM_EINVAL, NFM_ERANGE, NFM_EDEVICE, NFM_ESTATE, NFM_ESIZE = 0, -1, -2, -3, -4, -5
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "EDEVICE", -4: "ESTATE", -5: "ESIZE"}
+
+
+class NfmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("n_real", C.c_int32), ("L", C.POINTER(C.c_int32)), ("walkers", C.POINTER(C.c_int32)),
+                ("disorder_seed", C.c_uint64), ("walker_seed", C.c_uint64), ("first_real_id", C.c_uint32),
+                ("trace_capacity", C.c_int32)]
+
+
+WALKER_DTYPE = np.dtype([("E", np.int32), ("E_min", np.int32), ("rt_state", np.int32), ("new_min", np.int32),
+                         ("rt_count", np.uint64), ("t_first", np.uint64), ("t_last", np.uint64)], align=True)
+REAL_DTYPE = np.dtype([("rt_count", np.uint64), ("rt_time", np.uint64), ("E_min", np.int32), ("new_min", np.int32),
+                       ("walkers_with_trips", np.int32), ("pad", np.int32), ("reserved", np.uint64)], align=True)
+
+_lib = None
+
+
+def lib():
+    """Load libnfm.so; raise if it is missing (there is no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libnfm.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_size_t
+    sig = {
+        "nfm_workspace_bytes": (i32, [C.POINTER(BatchDesc), C.POINTER(sz)]),
+        "nfm_create": (i32, [C.POINTER(vp), C.POINTER(BatchDesc), vp, sz, C.c_int, vp]),
+        "nfm_destroy": (None, [vp]),
+        "nfm_last_error": (C.c_char_p, [vp]),
+        "nfm_n_real": (i32, [vp]),
+        "nfm_n_walkers": (i64, [vp]),
+        "nfm_levels": (i32, [vp, i32]),
+        "nfm_e_base": (i32, [vp, i32]),
+        "nfm_level_offset": (i64, [vp, i32]),
+        "nfm_levels_total": (i64, [vp]),
+        "nfm_walker_offset": (i64, [vp, i32]),
+        "nfm_sweep_counter": (u64, [vp]),
+        "nfm_init_couplings": (i32, [vp]),
+        "nfm_set_couplings": (i32, [vp, i32, i32, vp]),
+        "nfm_get_couplings": (i32, [vp, i32, i32, vp]),
+        "nfm_init_spins": (i32, [vp]),
+        "nfm_set_spins": (i32, [vp, i64, i64, vp]),
+        "nfm_get_spins": (i32, [vp, i64, i64, vp]),
+        "nfm_compute_energies": (i32, [vp]),
+        "nfm_set_thresholds": (i32, [vp, i32, vp, i32, i32]),
+        "nfm_get_thresholds": (i32, [vp, i32, vp, C.POINTER(i32), C.POINTER(i32)]),
+        "nfm_set_weights_lnw": (i32, [vp, vp, vp, vp]),
+        "nfm_set_rt_bounds": (i32, [vp, i32, i32, i32]),
+        "nfm_run_sweeps": (i32, [vp, u64]),
+        "nfm_read_histograms": (i32, [vp, vp, C.c_int]),
+        "nfm_reset_histograms": (i32, [vp]),
+        "nfm_read_walkers": (i32, [vp, vp]),
+        "nfm_read_realizations": (i32, [vp, vp]),
+        "nfm_read_trace": (i32, [vp, vp, C.POINTER(i32)]),
+        "nfm_reset_trace": (i32, [vp]),
+        "nfm_sync": (i32, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _desc(Ls: Sequence[int], walkers: Sequence[int], disorder_seed: int, walker_seed: int,
+          first_real_id: int, trace_capacity: int):
+    La = np.ascontiguousarray(Ls, np.int32)
+    Wa = np.ascontiguousarray(walkers, np.int32)
+    d = BatchDesc(len(La), La.ctypes.data_as(C.POINTER(C.c_int32)), Wa.ctypes.data_as(C.POINTER(C.c_int32)),
+                  disorder_seed, walker_seed, first_real_id, trace_capacity)
+    return d, (La, Wa)
+
+
+def workspace_bytes(Ls, walkers, trace_capacity=0) -> int:
+    d, keep = _desc(Ls, walkers, 0, 0, 0, trace_capacity)
+    n = C.c_size_t()
+    st = lib().nfm_workspace_bytes(C.byref(d), C.byref(n))
+    if st != NFM_OK:
+        raise NfmError(st, "invalid batch description")
+    return n.value
+
+
+def pack_couplings(J: np.ndarray, L: int) -> np.ndarray:
+    """ABI coupling words of one realization from +-1 couplings J[d*N + i]."""
+    N = L ** 3
+    JW = (N + 31) // 32
+    bits = (np.asarray(J).reshape(3, N) < 0).astype(np.uint32)
+    out = np.zeros((3, JW * 32), np.uint32)
+    out[:, :N] = bits
+    w = out.reshape(3, JW, 32) << np.arange(32, dtype=np.uint32)
+    return np.bitwise_or.reduce(w, axis=2).reshape(-1).astype(np.uint32)
+
+
+def unpack_couplings(words: np.ndarray, L: int) -> np.ndarray:
+    N = L ** 3
+    JW = (N + 31) // 32
+    w = np.asarray(words, np.uint32).reshape(3, JW, 1)
+    bits = ((w >> np.arange(32, dtype=np.uint32)) & 1).reshape(3, JW * 32)[:, :N]
+    return np.where(bits.reshape(-1) == 1, -1, 1).astype(np.int8)
+
+
+class Batch:
+    """One context of libnfm over a torch-allocated device workspace."""
+
+    def __init__(self, Ls: Sequence[int], walkers: Sequence[int], disorder_seed: int = 0, walker_seed: int = 0,
+                 first_real_id: int = 0, trace_capacity: int = 0, device: int = 0, stream=None):
+        import torch
+        self._lib = lib()
+        self.Ls = np.ascontiguousarray(Ls, np.int32)
+        self.walkers = np.ascontiguousarray(walkers, np.int32)
+        self.trace_capacity = trace_capacity
+        d, self._keep = _desc(self.Ls, self.walkers, disorder_seed, walker_seed, first_real_id, trace_capacity)
+        n = C.c_size_t()
+        self._check(self._lib.nfm_workspace_bytes(C.byref(d), C.byref(n)), "workspace size")
+        self.device = torch.device("cuda", device)
+        self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        ctx = C.c_void_p()
+        self._check(self._lib.nfm_create(C.byref(ctx), C.byref(d), C.c_void_p(aligned), n.value, device,
+                                         C.c_void_p(stream.cuda_stream)), "create")
+        self.ctx = ctx
+
+    def _check(self, st, what):
+        if st != NFM_OK:
+            msg = self._lib.nfm_last_error(self.ctx).decode() if getattr(self, "ctx", None) else what
+            raise NfmError(st, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self._lib.nfm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # geometry
+    @property
+    def n_real(self) -> int:
+        return int(self._lib.nfm_n_real(self.ctx))
+
+    @property
+    def n_walkers(self) -> int:
+        return int(self._lib.nfm_n_walkers(self.ctx))
+
+    def levels(self, r: int) -> int:
+        return int(self._lib.nfm_levels(self.ctx, r))
+
+    def e_base(self, r: int) -> int:
+        return int(self._lib.nfm_e_base(self.ctx, r))
+
+    def level_offset(self, r: int) -> int:
+        return int(self._lib.nfm_level_offset(self.ctx, r))
+
+    @property
+    def levels_total(self) -> int:
+        return int(self._lib.nfm_levels_total(self.ctx))
+
+    def walker_offset(self, r: int) -> int:
+        return int(self._lib.nfm_walker_offset(self.ctx, r))
+
+    @property
+    def sweep_counter(self) -> int:
+        return int(self._lib.nfm_sweep_counter(self.ctx))
+
+    # couplings and spins
+    def init_couplings(self):
+        self._check(self._lib.nfm_init_couplings(self.ctx), "init_couplings")
+
+    def set_couplings(self, r0: int, words: np.ndarray):
+        words = np.ascontiguousarray(words, np.uint32)
+        L = int(self.Ls[r0])
+        per = 3 * ((L ** 3 + 31) // 32)
+        count = words.size // per
+        self._check(self._lib.nfm_set_couplings(self.ctx, r0, count, words.ctypes.data), "set_couplings")
+
+    def get_couplings(self, r0: int, count: int = 1) -> np.ndarray:
+        n = sum(3 * ((int(self.Ls[r]) ** 3 + 31) // 32) for r in range(r0, r0 + count))
+        out = np.zeros(n, np.uint32)
+        self._check(self._lib.nfm_get_couplings(self.ctx, r0, count, out.ctypes.data), "get_couplings")
+        return out
+
+    def init_spins(self):
+        self._check(self._lib.nfm_init_spins(self.ctx), "init_spins")
+
+    def _walker_sizes(self, w0: int, count: int):
+        sizes = []
+        for r in range(self.n_real):
+            off, W, N = self.walker_offset(r), int(self.walkers[r]), int(self.Ls[r]) ** 3
+            lo, hi = max(w0, off), min(w0 + count, off + W)
+            if hi > lo:
+                sizes.append((hi - lo) * N)
+        return sum(sizes)
+
+    def set_spins(self, w0: int, S: np.ndarray):
+        S = np.ascontiguousarray(S, np.int8)
+        N = int(self.Ls[self._real_of(w0)]) ** 3
+        count = S.size // N if S.ndim == 1 else S.shape[0]
+        self._check(self._lib.nfm_set_spins(self.ctx, w0, count, S.ctypes.data), "set_spins")
+
+    def get_spins(self, w0: int, count: int) -> np.ndarray:
+        out = np.zeros(self._walker_sizes(w0, count), np.int8)
+        self._check(self._lib.nfm_get_spins(self.ctx, w0, count, out.ctypes.data), "get_spins")
+        return out
+
+    def _real_of(self, w: int) -> int:
+        for r in range(self.n_real):
+            if self.walker_offset(r) <= w < self.walker_offset(r) + int(self.walkers[r]):
+                return r
+        raise IndexError(w)
+
+    def compute_energies(self):
+        self._check(self._lib.nfm_compute_energies(self.ctx), "compute_energies")
+
+    # tables
+    def set_thresholds(self, r: int, thr: np.ndarray, row0: int):
+        thr = np.ascontiguousarray(thr, np.uint32).reshape(-1, 8)
+        self._check(self._lib.nfm_set_thresholds(self.ctx, r, thr.ctypes.data, row0, thr.shape[0]), "set_thresholds")
+
+    def get_thresholds(self, r: int):
+        row0, rows = C.c_int32(), C.c_int32()
+        self._check(self._lib.nfm_get_thresholds(self.ctx, r, None, C.byref(row0), C.byref(rows)), "get_thresholds")
+        out = np.zeros((max(rows.value, 1), 8), np.uint32)
+        self._check(self._lib.nfm_get_thresholds(self.ctx, r, out.ctypes.data, C.byref(row0), C.byref(rows)),
+                    "get_thresholds")
+        return out[:rows.value], row0.value
+
+    def set_weights_lnw(self, lnw: np.ndarray, k_lo: Sequence[int], k_top: Sequence[int]):
+        lnw = np.ascontiguousarray(lnw, np.float64)
+        assert lnw.size == self.levels_total
+        klo = np.ascontiguousarray(k_lo, np.int32)
+        ktop = np.ascontiguousarray(k_top, np.int32)
+        self._check(self._lib.nfm_set_weights_lnw(self.ctx, lnw.ctypes.data, klo.ctypes.data, ktop.ctypes.data),
+                    "set_weights_lnw")
+
+    def set_rt_bounds(self, r: int, e_bot: int, e_top: int):
+        self._check(self._lib.nfm_set_rt_bounds(self.ctx, r, e_bot, e_top), "set_rt_bounds")
+
+    # sampling and read-back
+    def run_sweeps(self, n: int):
+        self._check(self._lib.nfm_run_sweeps(self.ctx, n), "run_sweeps")
+
+    def read_histograms(self, reset: bool = False) -> np.ndarray:
+        out = np.zeros(self.levels_total, np.uint64)
+        self._check(self._lib.nfm_read_histograms(self.ctx, out.ctypes.data, 1 if reset else 0), "read_histograms")
+        return out
+
+    def reset_histograms(self):
+        self._check(self._lib.nfm_reset_histograms(self.ctx), "reset_histograms")
+
+    def read_walkers(self) -> np.ndarray:
+        out = np.zeros(self.n_walkers, WALKER_DTYPE)
+        self._check(self._lib.nfm_read_walkers(self.ctx, out.ctypes.data), "read_walkers")
+        return out
+
+    def read_realizations(self) -> np.ndarray:
+        out = np.zeros(self.n_real, REAL_DTYPE)
+        self._check(self._lib.nfm_read_realizations(self.ctx, out.ctypes.data), "read_realizations")
+        return out
+
+    def read_trace(self):
+        n = C.c_int32()
+        out = np.zeros((self.n_walkers, max(self.trace_capacity, 0)), np.int32)
+        self._check(self._lib.nfm_read_trace(self.ctx, out.ctypes.data if out.size else None, C.byref(n)),
+                    "read_trace")
+        return out[:, :n.value]
+
+    def reset_trace(self):
+        self._check(self._lib.nfm_reset_trace(self.ctx), "reset_trace")
+
+    def sync(self):
+        self._check(self._lib.nfm_sync(self.ctx), "sync")
