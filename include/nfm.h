@@ -189,6 +189,55 @@ nfm_status nfm_read_realizations(nfm_ctx* ctx, nfm_real_stats* host_dst); /* all
 nfm_status nfm_read_trace(nfm_ctx* ctx, int32_t* host_dst, int32_t* n_valid);
 nfm_status nfm_reset_trace(nfm_ctx* ctx);
 
+/* Inject histograms (nfm_levels_total() uint64, same layout as nfm_read_histograms). */
+nfm_status nfm_set_histograms(nfm_ctx* ctx, const uint64_t* host_src);
+/* Clear every walker's round-trip state, counters and new_min (E and E_min kept), e.g. before
+ * a production run (Sec. III: round trips are counted in production). */
+nfm_status nfm_reset_round_trips(nfm_ctx* ctx);
+
+/* Weight iteration on the device (Sec. II: the DOS estimate is iterated once per realization,
+ * with power-law shaped targets, and reused by every ensemble). Profiles: 0 flat (Eq. (3)),
+ * 1 power law (Eqs. (4), (5): ln P = alpha ln((E - E_g + dE)/(dE - E_g)), E_g the lowest energy
+ * found; dE > 0, alpha <= 0), 2 the 1/k-ensemble (Eq. (7)).
+ * State per realization: DOS steps b(k) = S(k+1) - S(k) and their accumulated weights p(k)
+ * (FP64, nfm_level_offset layout), visited levels, k_lo (lowest level found), k_top (lowest
+ * level with E >= 0). Weights lnW = -S + ln P on [k_lo, k_top] with S(k_top) = 0.
+ *
+ * nfm_rec_init: b = p = 0, k_lo from the walkers' minima; builds weights and tables, sets the
+ *   round-trip bounds to e_bot = E(k_lo), e_top = 0, clears the histograms.
+ * nfm_rec_update: one update from the histograms accumulated since the last init/update
+ *   (synchronizes): k_lo <- min(k_lo, walkers' minima) (new levels take b(k_lo), p = 0); for
+ *   consecutive visited levels k < k': est = [ln H(k') - lnW(k')] - [ln H(k) - lnW(k)] (lnW
+ *   continued below the old k_lo with its lowest step), g0 = H(k)H(k')/(H(k)+H(k')), p(k) += g0,
+ *   b(k) += (g0/p(k)) (est - (b(k)+...+b(k'-1))); flatness = min/mean of H/P over levels ever
+ *   visited in [k_lo, k_top]; converged iff flatness >= f_tol and k_lo unchanged. Then the next
+ *   weights (profile re-anchored at the new k_lo), tables and bounds; histograms cleared.
+ *   host_info (optional) receives every realization's nfm_rec_info.
+ * nfm_rec_production: tables from the current estimate with the given profile (flat lnW = -S,
+ *   power law -S + ln P, 1/k -ln sum_{j<=k} exp S), bounds e_bot = E(k_lo), e_top = 0,
+ *   histograms cleared. */
+typedef struct {
+  int32_t k_lo, k_top;
+  int32_t profile;
+  int32_t converged;     /* last update: flat to f_tol and no new minimum */
+  int32_t iterations;    /* updates done */
+  int32_t k_lo_changed;  /* last update lowered k_lo */
+  double pl_dE, pl_alpha;
+  double flatness;       /* last update */
+} nfm_rec_info;
+
+nfm_status nfm_rec_init(nfm_ctx* ctx, int32_t profile, double pl_dE, double pl_alpha);
+nfm_status nfm_rec_update(nfm_ctx* ctx, double f_tol, nfm_rec_info* host_info);
+nfm_status nfm_rec_production(nfm_ctx* ctx, int32_t profile, double pl_dE, double pl_alpha);
+nfm_status nfm_rec_read_info(nfm_ctx* ctx, nfm_rec_info* host_info);
+/* Read / write one realization's recursion state (arrays of 3N/2+1 entries; any pointer of
+ * rec_get_state may be NULL). rec_set_state also marks the recursion as initialized. */
+nfm_status nfm_rec_get_state(nfm_ctx* ctx, int32_t r, double* b, double* p, double* S, double* lnP,
+                             double* lnW, uint8_t* visited, nfm_rec_info* info);
+nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const double* p,
+                             const double* lnP, const double* lnW, const uint8_t* visited,
+                             const nfm_rec_info* info);
+
 nfm_status nfm_sync(nfm_ctx* ctx);
 
 #ifdef __cplusplus

@@ -24,6 +24,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t reals, waves, jabi, jk, spins, ws_i32, ws_u64, tables, hist, lnw, klo, ktop, trace, rstats, staging, total;
+  size_t recs, rec_f64, rec_vis;
   int64_t total_walkers, total_waves, levels_total, jabi_words, jk_words, spin_words, table_words;
   size_t staging_bytes;
 };
@@ -85,6 +86,9 @@ bool make_layout(const nfm_batch_desc* d, Layout* lay, std::string* why) {
   l.trace = take(4 * (size_t)l.total_walkers * (size_t)d->trace_capacity);
   l.rstats = take(sizeof(nfm::RealStatsDev) * d->n_real);
   l.staging = take(l.staging_bytes);
+  l.recs = take(sizeof(nfm::RecInfo) * d->n_real);
+  l.rec_f64 = take(8 * 5 * (size_t)l.levels_total);
+  l.rec_vis = take((size_t)l.levels_total);
   l.total = off;
   *lay = l;
   return true;
@@ -121,6 +125,20 @@ struct nfm_ctx {
   int32_t* d_trace() { return (int32_t*)(ws + lay.trace); }
   nfm::RealStatsDev* d_rstats() { return (nfm::RealStatsDev*)(ws + lay.rstats); }
   void* d_staging() { return ws + lay.staging; }
+  nfm::RecInfo* d_recs() { return (nfm::RecInfo*)(ws + lay.recs); }
+  nfm::RecArrays rec_arrays() {
+    nfm::RecArrays a;
+    double* f = (double*)(ws + lay.rec_f64);
+    const int64_t n = lay.levels_total;
+    a.b = f;
+    a.p = f + n;
+    a.S = f + 2 * n;
+    a.lnP = f + 3 * n;
+    a.lnW = f + 4 * n;
+    a.visited = (unsigned char*)(ws + lay.rec_vis);
+    return a;
+  }
+  bool rec_ready = false;
   nfm::WalkerState walker_state() {
     nfm::WalkerState s;
     const int64_t W = lay.total_walkers;
@@ -594,6 +612,117 @@ nfm_status nfm_reset_trace(nfm_ctx* c) {
 nfm_status nfm_sync(nfm_ctx* c) {
   NFM_GUARD(c);
   NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+
+nfm_status nfm_set_histograms(nfm_ctx* c, const uint64_t* host_src) {
+  NFM_GUARD(c);
+  if (!host_src) return fail(c, NFM_EINVAL, "set_histograms: null pointer");
+  NFM_HIP(c, hipMemcpyAsync(c->d_hist(), host_src, 8 * (size_t)c->lay.levels_total, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_reset_round_trips(nfm_ctx* c) {
+  NFM_GUARD(c);
+  const int64_t W = c->lay.total_walkers;
+  nfm::WalkerState ws = c->walker_state();
+  NFM_HIP(c, hipMemsetAsync(ws.rt_state, 0, 4 * (size_t)W, c->stream));
+  NFM_HIP(c, hipMemsetAsync(ws.new_min, 0, 4 * (size_t)W, c->stream));
+  NFM_HIP(c, hipMemsetAsync(c->ws + c->lay.ws_u64, 0, 8 * 3 * (size_t)W, c->stream));
+  return NFM_OK;
+}
+
+static bool valid_profile(int profile, double dE, double alpha) {
+  if (profile < 0 || profile > 2) return false;
+  if (profile == 1 && !(dE > 0.0 && alpha <= 0.0)) return false;
+  return true;
+}
+
+nfm_status nfm_rec_init(nfm_ctx* c, int32_t profile, double pl_dE, double pl_alpha) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "rec_init: couplings not set");
+  if (!valid_profile(profile, pl_dE, pl_alpha)) return fail(c, NFM_EINVAL, "rec_init: bad profile");
+  hipError_t e = nfm::launch_rec_init(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->walker_state(), profile,
+                                      pl_dE, pl_alpha, c->d_tables(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_init: ") + hipGetErrorString(e));
+  NFM_HIP(c, hipMemsetAsync(c->d_hist(), 0, 8 * (size_t)c->lay.levels_total, c->stream));
+  c->rec_ready = true;
+  return pull_reals(c);
+}
+
+nfm_status nfm_rec_update(nfm_ctx* c, double f_tol, nfm_rec_info* host_info) {
+  NFM_GUARD(c);
+  if (!c->rec_ready) return fail(c, NFM_ESTATE, "rec_update: call nfm_rec_init first");
+  if (!(f_tol >= 0.0 && f_tol <= 1.0)) return fail(c, NFM_EINVAL, "rec_update: f_tol outside [0, 1]");
+  hipError_t e = nfm::launch_rec_update(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->walker_state(),
+                                        c->d_hist(), c->d_tables(), f_tol, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_update: ") + hipGetErrorString(e));
+  nfm_status st = pull_reals(c);
+  if (st != NFM_OK || !host_info) return st;
+  static_assert(sizeof(nfm_rec_info) == sizeof(nfm::RecInfo), "layout");
+  NFM_HIP(c, hipMemcpyAsync(host_info, c->d_recs(), sizeof(nfm_rec_info) * c->n_real, hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_rec_production(nfm_ctx* c, int32_t profile, double pl_dE, double pl_alpha) {
+  NFM_GUARD(c);
+  if (!c->rec_ready) return fail(c, NFM_ESTATE, "rec_production: call nfm_rec_init first");
+  if (!valid_profile(profile, pl_dE, pl_alpha)) return fail(c, NFM_EINVAL, "rec_production: bad profile");
+  hipError_t e = nfm::launch_rec_production(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->d_tables(),
+                                            profile, pl_dE, pl_alpha, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_production: ") + hipGetErrorString(e));
+  NFM_HIP(c, hipMemsetAsync(c->d_hist(), 0, 8 * (size_t)c->lay.levels_total, c->stream));
+  return pull_reals(c);
+}
+
+nfm_status nfm_rec_read_info(nfm_ctx* c, nfm_rec_info* host_info) {
+  NFM_GUARD(c);
+  if (!host_info) return fail(c, NFM_EINVAL, "rec_read_info: null pointer");
+  NFM_HIP(c, hipMemcpyAsync(host_info, c->d_recs(), sizeof(nfm_rec_info) * c->n_real, hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_rec_get_state(nfm_ctx* c, int32_t r, double* b, double* p, double* S, double* lnP, double* lnW,
+                             uint8_t* visited, nfm_rec_info* info) {
+  NFM_GUARD(c);
+  if (r < 0 || r >= c->n_real) return fail(c, NFM_EINVAL, "rec_get_state: bad realization");
+  const int64_t off = c->reals[r].level_off;
+  const size_t n = (size_t)nfm::level_capacity(c->reals[r].N);
+  nfm::RecArrays a = c->rec_arrays();
+  double* src[5] = {a.b, a.p, a.S, a.lnP, a.lnW};
+  double* dst[5] = {b, p, S, lnP, lnW};
+  for (int i = 0; i < 5; ++i)
+    if (dst[i]) NFM_HIP(c, hipMemcpyAsync(dst[i], src[i] + off, 8 * n, hipMemcpyDeviceToHost, c->stream));
+  if (visited) NFM_HIP(c, hipMemcpyAsync(visited, a.visited + off, n, hipMemcpyDeviceToHost, c->stream));
+  if (info) NFM_HIP(c, hipMemcpyAsync(info, c->d_recs() + r, sizeof(nfm_rec_info), hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_rec_set_state(nfm_ctx* c, int32_t r, const double* b, const double* p, const double* lnP,
+                             const double* lnW, const uint8_t* visited, const nfm_rec_info* info) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "rec_set_state: couplings not set");
+  if (r < 0 || r >= c->n_real || !b || !p || !lnP || !lnW || !visited || !info)
+    return fail(c, NFM_EINVAL, "rec_set_state: bad arguments");
+  const RealInfo& ri = c->reals[r];
+  if (info->k_lo < 0 || info->k_top >= ri.K || info->k_lo > info->k_top || !valid_profile(info->profile, info->pl_dE, info->pl_alpha))
+    return fail(c, NFM_EINVAL, "rec_set_state: bad level range or profile");
+  const int64_t off = ri.level_off;
+  const size_t n = (size_t)nfm::level_capacity(ri.N);
+  nfm::RecArrays a = c->rec_arrays();
+  NFM_HIP(c, hipMemcpyAsync(a.b + off, b, 8 * n, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(a.p + off, p, 8 * n, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(a.lnP + off, lnP, 8 * n, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(a.lnW + off, lnW, 8 * n, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(a.visited + off, visited, n, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(c->d_recs() + r, info, sizeof(nfm_rec_info), hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  c->rec_ready = true;
   return NFM_OK;
 }
 

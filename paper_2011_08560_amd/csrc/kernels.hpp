@@ -31,6 +31,16 @@ hipError_t launch_reduce_real(const RealInfo* reals, int n_real, WalkerState ws,
 hipError_t launch_build_tables(RealInfo* reals, int n_real, const double* lnw, const int32_t* k_lo,
                                const int32_t* k_top, uint32_t* tables, hipStream_t s);
 
+// recursion.hip
+hipError_t launch_rec_init(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws, int profile,
+                           double pl_dE, double pl_alpha, uint32_t* tables, hipStream_t s);
+hipError_t launch_rec_weights(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, uint32_t* tables,
+                              int set_bounds, hipStream_t s);
+hipError_t launch_rec_update(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws,
+                             unsigned long long* hist, uint32_t* tables, double f_tol, hipStream_t s);
+hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, uint32_t* tables,
+                                 int profile, double pl_dE, double pl_alpha, hipStream_t s);
+
 // sweep.hip
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s);
 bool sweep_supported(int L);

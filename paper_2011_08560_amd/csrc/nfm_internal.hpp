@@ -71,4 +71,25 @@ struct SweepArgs {
   uint64_t walker_seed;
 };
 
+// Weight-recursion state of one realization (device and host mirror, same layout as nfm_rec_info).
+struct RecInfo {
+  int32_t k_lo, k_top;       // estimate defined on [k_lo, k_top]; k_top = lowest level with E >= 0
+  int32_t profile;           // 0 flat, 1 power law, 2 1/k
+  int32_t converged;         // last update: flat to f_tol and no new minimum
+  int32_t iterations;        // updates done
+  int32_t k_lo_changed;      // last update lowered k_lo
+  double pl_dE, pl_alpha;    // power-law parameters of Eq. (5)
+  double flatness;           // min/mean of H/P over visited levels, last update
+};
+
+// Per-level FP64 arrays of the recursion (indexed by level offset + level).
+struct RecArrays {
+  double* b;                 // DOS steps S(k+1) - S(k)
+  double* p;                 // accumulated weights of the steps
+  double* S;                 // ln Omega estimate, S(k_top) = 0
+  double* lnP;               // target profile used for the current weights
+  double* lnW;               // current log-weights
+  unsigned char* visited;    // level ever visited
+};
+
 }  // namespace nfm

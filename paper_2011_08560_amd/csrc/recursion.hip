@@ -1,0 +1,231 @@
+// Weight iteration on the device (Sec. II): the density-of-states estimate is refined from the
+// histograms of the last sampling round, re-anchored at new minima, and turned into the next
+// log-weights and threshold table, all without leaving the GPU.
+//
+// Estimate: DOS steps b(k) = S(k+1) - S(k), S = ln Omega up to a constant, S(k_top) = 0.
+// Profiles (ln P): flat 0; power law alpha ln((E - E_g + dE)/(dE - E_g)), Eq. (5) with E_g the
+// lowest energy found; 1/k: S(k) - ln sum_{j=k_lo..k} exp S(j), Eq. (7). Weights lnW = -S + ln P
+// (Eqs. (3), (4)). Update (accumulated statistics, Berg's multicanonical recursion written for a
+// target profile): for consecutive visited levels k < k',
+//   est = [ln H(k') - lnW(k')] - [ln H(k) - lnW(k)],  g0 = H(k) H(k') / (H(k) + H(k')),
+//   p(k) += g0,  b(k) += (g0 / p(k)) (est - (b(k) + ... + b(k'-1))).
+// The sequential parts (prefix sums over levels) run on one thread per realization in the same
+// operation order as the oracle; the table is built by all threads of the block.
+#include "kernels.hpp"
+#include "table_builder.hpp"
+
+namespace nfm {
+
+__device__ __forceinline__ double rec_lnP_power(double E, double E_g, double dE, double alpha) {
+  return alpha * log(E / (dE - E_g) + 1.0);
+}
+
+// S, ln P and lnW on [k_lo, k_top] from b (one thread).
+__device__ void rec_weights_seq(const RecInfo& ri, int e_base, const double* b, double* S, double* lnP, double* lnW) {
+  const int k_lo = ri.k_lo, k_top = ri.k_top;
+  S[k_top] = 0.0;
+  for (int k = k_top - 1; k >= k_lo; --k) S[k] = S[k + 1] - b[k];
+  const double E_g = (double)(e_base + 4 * k_lo);
+  double acc = 0.0;
+  for (int k = k_lo; k <= k_top; ++k) {
+    const double E = (double)(e_base + 4 * k);
+    double lp;
+    if (ri.profile == 0) {
+      lp = 0.0;
+    } else if (ri.profile == 1) {
+      lp = rec_lnP_power(E, E_g, ri.pl_dE, ri.pl_alpha);
+    } else {
+      if (k == k_lo) {
+        acc = S[k];
+      } else {
+        const double m = acc > S[k] ? acc : S[k];
+        acc = m + log1p(exp(-fabs(acc - S[k])));
+      }
+      lp = S[k] - acc;
+    }
+    lnP[k] = lp;
+    lnW[k] = -S[k] + lp;
+  }
+}
+
+// One realization per block: weights from the current estimate, table, round-trip bounds.
+__global__ void k_rec_weights(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A,
+                              uint32_t* __restrict__ tables, int set_bounds) {
+  RealInfo* rp = reals + blockIdx.x;
+  RecInfo* rc = recs + blockIdx.x;
+  const int64_t off = rp->level_off;
+  if (threadIdx.x == 0) {
+    rec_weights_seq(*rc, rp->e_base, A.b + off, A.S + off, A.lnP + off, A.lnW + off);
+    if (set_bounds) {
+      rp->e_bot = rp->e_base + 4 * rc->k_lo;
+      rp->e_top = 0;
+    }
+  }
+  __syncthreads();
+  build_table_block(rp, A.lnW + off, rc->k_lo, rc->k_top, tables);
+}
+
+// Initial state: b = p = 0, nothing visited, k_lo = lowest level of any walker's minimum.
+__global__ void k_rec_init(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A, WalkerState ws,
+                           int profile, double pl_dE, double pl_alpha) {
+  RealInfo* rp = reals + blockIdx.x;
+  RecInfo* rc = recs + blockIdx.x;
+  const int64_t off = rp->level_off;
+  const int cap = level_capacity(rp->N);
+  for (int k = threadIdx.x; k < cap; k += blockDim.x) {
+    A.b[off + k] = 0.0;
+    A.p[off + k] = 0.0;
+    A.S[off + k] = 0.0;
+    A.lnP[off + k] = 0.0;
+    A.lnW[off + k] = 0.0;
+    A.visited[off + k] = 0;
+  }
+  __shared__ int s_min;
+  if (threadIdx.x == 0) s_min = 0x7fffffff;
+  __syncthreads();
+  int m = 0x7fffffff;
+  for (int w = threadIdx.x; w < rp->walkers; w += blockDim.x) m = min(m, ws.E_min[rp->walker_off + w]);
+  atomicMin(&s_min, m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int k_top = (-rp->e_base + 3) / 4;  // lowest level with E >= 0
+    int k_lo = (s_min - rp->e_base) / 4;
+    if (k_lo > k_top) k_lo = k_top;
+    rc->k_lo = k_lo;
+    rc->k_top = k_top;
+    rc->profile = profile;
+    rc->pl_dE = pl_dE;
+    rc->pl_alpha = pl_alpha;
+    rc->flatness = 0.0;
+    rc->converged = 0;
+    rc->iterations = 0;
+    rc->k_lo_changed = 0;
+  }
+}
+
+// One update from the histogram of the last sampling round, then the next weights and table.
+__global__ void k_rec_update(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A, WalkerState ws,
+                             unsigned long long* __restrict__ hist, uint32_t* __restrict__ tables, double f_tol) {
+  RealInfo* rp = reals + blockIdx.x;
+  RecInfo* rc = recs + blockIdx.x;
+  const int64_t off = rp->level_off;
+  __shared__ int s_min;
+  if (threadIdx.x == 0) s_min = 0x7fffffff;
+  __syncthreads();
+  int mn = 0x7fffffff;
+  for (int w = threadIdx.x; w < rp->walkers; w += blockDim.x) mn = min(mn, ws.E_min[rp->walker_off + w]);
+  atomicMin(&s_min, mn);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long* H = hist + off;
+    double* b = A.b + off;
+    double* p = A.p + off;
+    const double* lnW = A.lnW + off;
+    const double* lnP = A.lnP + off;
+    unsigned char* visited = A.visited + off;
+    const int k_lo_used = rc->k_lo, k_top = rc->k_top;
+    int k_min_seen = (s_min - rp->e_base) / 4;
+    if (k_min_seen > k_lo_used) k_min_seen = k_lo_used;
+    const int k_lo = k_min_seen;
+    for (int k = k_lo; k < k_lo_used; ++k) {
+      b[k] = b[k_lo_used];
+      p[k] = 0.0;
+    }
+    const double d_lo = (k_lo_used < k_top) ? lnW[k_lo_used + 1] - lnW[k_lo_used] : 0.0;
+    auto lnw_at = [&](int k) {
+      return k >= k_lo_used ? lnW[k] : lnW[k_lo_used] - (double)(k_lo_used - k) * d_lo;
+    };
+    auto lnp_at = [&](int k) { return k >= k_lo_used ? lnP[k] : lnP[k_lo_used]; };
+    int prev = -1;
+    for (int k = k_lo; k <= k_top; ++k) {
+      if (H[k] == 0) continue;
+      if (prev >= 0) {
+        const double Hk = (double)H[prev], Hk1 = (double)H[k];
+        const double est = (log(Hk1) - lnw_at(k)) - (log(Hk) - lnw_at(prev));
+        double span = 0.0;
+        for (int j = prev; j < k; ++j) span += b[j];
+        const double g0 = Hk * Hk1 / (Hk + Hk1);
+        p[prev] += g0;
+        b[prev] += (g0 / p[prev]) * (est - span);
+      }
+      prev = k;
+    }
+    double mnv = 0.0, sum = 0.0;
+    int n = 0;
+    for (int k = k_lo; k <= k_top; ++k) {
+      if (H[k] > 0) visited[k] = 1;
+      if (!visited[k]) continue;
+      const double v = (double)H[k] / exp(lnp_at(k));
+      if (n == 0 || v < mnv) mnv = v;
+      sum += v;
+      ++n;
+    }
+    const double flat = (n > 0 && sum > 0.0) ? mnv / (sum / (double)n) : 0.0;
+    rc->k_lo_changed = (k_lo != k_lo_used);
+    rc->k_lo = k_lo;
+    rc->flatness = flat;
+    rc->converged = (flat >= f_tol && k_lo == k_lo_used) ? 1 : 0;
+    rc->iterations += 1;
+    // next weights (re-anchored profile), bounds for the next round
+    rec_weights_seq(*rc, rp->e_base, b, A.S + off, A.lnP + off, A.lnW + off);
+    rp->e_bot = rp->e_base + 4 * k_lo;
+    rp->e_top = 0;
+  }
+  __syncthreads();
+  build_table_block(rp, A.lnW + off, rc->k_lo, rc->k_top, tables);
+  const int cap = level_capacity(rp->N);
+  for (int k = threadIdx.x; k < cap; k += blockDim.x) hist[off + k] = 0ull;
+}
+
+// Production weights from the final estimate (Sec. II: the DOS is determined once and reused by
+// every ensemble): flat lnW = -S, power law -S + ln P_SH, 1/k -S + (S - ln sum exp S).
+__global__ void k_rec_production(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A,
+                                 uint32_t* __restrict__ tables, int profile, double pl_dE, double pl_alpha) {
+  if (threadIdx.x == 0) {
+    RecInfo* rc = recs + blockIdx.x;
+    rc->profile = profile;
+    rc->pl_dE = pl_dE;
+    rc->pl_alpha = pl_alpha;
+  }
+  __syncthreads();
+  RealInfo* rp = reals + blockIdx.x;
+  RecInfo* rc = recs + blockIdx.x;
+  const int64_t off = rp->level_off;
+  if (threadIdx.x == 0) {
+    rec_weights_seq(*rc, rp->e_base, A.b + off, A.S + off, A.lnP + off, A.lnW + off);
+    rp->e_bot = rp->e_base + 4 * rc->k_lo;
+    rp->e_top = 0;
+  }
+  __syncthreads();
+  build_table_block(rp, A.lnW + off, rc->k_lo, rc->k_top, tables);
+}
+
+hipError_t launch_rec_init(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws, int profile,
+                           double pl_dE, double pl_alpha, uint32_t* tables, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_init, dim3(n_real), dim3(256), 0, s, reals, recs, A, ws, profile, pl_dE, pl_alpha);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rec_weights, dim3(n_real), dim3(256), 0, s, reals, recs, A, tables, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_weights(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, uint32_t* tables,
+                              int set_bounds, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_weights, dim3(n_real), dim3(256), 0, s, reals, recs, A, tables, set_bounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_update(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws,
+                             unsigned long long* hist, uint32_t* tables, double f_tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_update, dim3(n_real), dim3(256), 0, s, reals, recs, A, ws, hist, tables, f_tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, uint32_t* tables,
+                                 int profile, double pl_dE, double pl_alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_production, dim3(n_real), dim3(256), 0, s, reals, recs, A, tables, profile, pl_dE,
+                     pl_alpha);
+  return hipGetLastError();
+}
+
+}  // namespace nfm

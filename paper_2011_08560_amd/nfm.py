@@ -36,6 +36,11 @@ WALKER_DTYPE = np.dtype([("E", np.int32), ("E_min", np.int32), ("rt_state", np.i
 REAL_DTYPE = np.dtype([("rt_count", np.uint64), ("rt_time", np.uint64), ("E_min", np.int32), ("new_min", np.int32),
                        ("walkers_with_trips", np.int32), ("pad", np.int32), ("reserved", np.uint64)], align=True)
 
+REC_DTYPE = np.dtype([("k_lo", np.int32), ("k_top", np.int32), ("profile", np.int32), ("converged", np.int32),
+                      ("iterations", np.int32), ("k_lo_changed", np.int32), ("pl_dE", np.float64),
+                      ("pl_alpha", np.float64), ("flatness", np.float64)], align=True)
+PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
+
 _lib = None
 
 
@@ -80,6 +85,14 @@ def lib():
         "nfm_read_trace": (i32, [vp, vp, C.POINTER(i32)]),
         "nfm_reset_trace": (i32, [vp]),
         "nfm_sync": (i32, [vp]),
+        "nfm_set_histograms": (i32, [vp, vp]),
+        "nfm_reset_round_trips": (i32, [vp]),
+        "nfm_rec_init": (i32, [vp, i32, C.c_double, C.c_double]),
+        "nfm_rec_update": (i32, [vp, C.c_double, vp]),
+        "nfm_rec_production": (i32, [vp, i32, C.c_double, C.c_double]),
+        "nfm_rec_read_info": (i32, [vp, vp]),
+        "nfm_rec_get_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "nfm_rec_set_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -303,3 +316,55 @@ class Batch:
 
     def sync(self):
         self._check(self._lib.nfm_sync(self.ctx), "sync")
+
+    # weight recursion
+    def set_histograms(self, H: np.ndarray):
+        H = np.ascontiguousarray(H, np.uint64)
+        assert H.size == self.levels_total
+        self._check(self._lib.nfm_set_histograms(self.ctx, H.ctypes.data), "set_histograms")
+
+    def reset_round_trips(self):
+        self._check(self._lib.nfm_reset_round_trips(self.ctx), "reset_round_trips")
+
+    def rec_init(self, profile: int = PROFILE_FLAT, pl_dE: float = 1.0, pl_alpha: float = 0.0):
+        self._check(self._lib.nfm_rec_init(self.ctx, profile, pl_dE, pl_alpha), "rec_init")
+
+    def rec_update(self, f_tol: float = 0.5) -> np.ndarray:
+        info = np.zeros(self.n_real, REC_DTYPE)
+        self._check(self._lib.nfm_rec_update(self.ctx, f_tol, info.ctypes.data), "rec_update")
+        return info
+
+    def rec_production(self, profile: int, pl_dE: float = 96.0, pl_alpha: float = -3.6):
+        self._check(self._lib.nfm_rec_production(self.ctx, profile, pl_dE, pl_alpha), "rec_production")
+
+    def rec_read_info(self) -> np.ndarray:
+        info = np.zeros(self.n_real, REC_DTYPE)
+        self._check(self._lib.nfm_rec_read_info(self.ctx, info.ctypes.data), "rec_read_info")
+        return info
+
+    def rec_get_state(self, r: int) -> dict:
+        n = 3 * int(self.Ls[r]) ** 3 // 2 + 1
+        out = {k: np.zeros(n, np.float64) for k in ("b", "p", "S", "lnP", "lnW")}
+        out["visited"] = np.zeros(n, np.uint8)
+        info = np.zeros(1, REC_DTYPE)
+        self._check(self._lib.nfm_rec_get_state(self.ctx, r, out["b"].ctypes.data, out["p"].ctypes.data,
+                                                out["S"].ctypes.data, out["lnP"].ctypes.data,
+                                                out["lnW"].ctypes.data, out["visited"].ctypes.data,
+                                                info.ctypes.data), "rec_get_state")
+        out["info"] = info[0]
+        return out
+
+    def rec_set_state(self, r: int, b, p, lnP, lnW, visited, k_lo: int, k_top: int, profile: int = PROFILE_FLAT,
+                      pl_dE: float = 1.0, pl_alpha: float = 0.0):
+        n = 3 * int(self.Ls[r]) ** 3 // 2 + 1
+        arr = [np.zeros(n, np.float64) for _ in range(4)]
+        for a, v in zip(arr, (b, p, lnP, lnW)):
+            a[:len(v)] = v
+        vis = np.zeros(n, np.uint8)
+        vis[:len(visited)] = visited
+        info = np.zeros(1, REC_DTYPE)
+        info["k_lo"], info["k_top"], info["profile"] = k_lo, k_top, profile
+        info["pl_dE"], info["pl_alpha"] = pl_dE, pl_alpha
+        self._check(self._lib.nfm_rec_set_state(self.ctx, r, arr[0].ctypes.data, arr[1].ctypes.data,
+                                                arr[2].ctypes.data, arr[3].ctypes.data, vis.ctypes.data,
+                                                info.ctypes.data), "rec_set_state")
