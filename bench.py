@@ -1,14 +1,16 @@
 """Benchmark of the multicanonical sampler on one MI355X.
 
-Workload (default): 1024 disorder realizations of the L = 6 bimodal EA spin glass,
-64 walkers each, power-law-target weight iteration (Sec. II of Muller, Schnabel,
-Janke); one step is one pass of the hot path over the batch: S sweeps of every
-walker (per-attempt minimum/round-trip bookkeeping, per-sweep histograms), then the
-per-realization reduction of the walker statistics. Synthetic seeded disorder.
+Workload (default, the L = 6 configuration): 1024 disorder realizations of the 3D bimodal EA
+spin glass, 64 walkers each, weight iteration towards the power-law target
+H(E) ~ (E - E_min + 1)^(-a), a = 1 (Eq. (5) with dE = 1, alpha = -a; Sec. II of Muller,
+Schnabel, Janke). One step is one pass of the hot path over the batch: S multicanonical sweeps
+of every walker (per-attempt minimum and round-trip bookkeeping, per-sweep histograms), then
+the device weight update (recursion, re-anchoring, flatness test, next weights and tables).
+Disorder is synthetic and seeded (±1 couplings with p = 1/2, as in the paper's own samples).
 
-Prints ONE JSON line (rank 0): spin-flip attempts per second of the whole job, the
-roofline of the sweep kernel (VALU-issue bound) and the CPU oracle's rate on a
-bounded sample of the same workload.
+Prints ONE JSON line: spin-flip attempts per second of the whole job, round trips per second,
+weight-iteration progress, the roofline of the sweep kernel (integer VALU issue) and the CPU
+oracle running the same iteration on a bounded sample.
 """
 from __future__ import annotations
 
@@ -25,96 +27,60 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic integer lane-operations per spin-flip attempt (see the design notes):
-# Philox4x32-10 share 10 (2.5 rounds x (2 wide products + 2 three-input xors)),
-# neighbour count 1, table address 2, acceptance 2, spin/energy update 2,
-# bookkeeping check 1.
+# Algorithmic integer lane-operations per spin-flip attempt:
+# Philox4x32-10 share 10 (2.5 rounds x (2 wide products + 2 three-input xors)), neighbour
+# count 1, table address 2, acceptance 2, spin/energy update 2, bookkeeping check 1.
 ALG_OPS_PER_ATTEMPT = 18.0
 # MI355X integer VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per cycle).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+SWEEPS_PER_LAUNCH = 1024  # the library splits runs into launches of at most this many sweeps
 
 CONFIGS = {
-    # name: (L, realizations, walkers per realization, sweeps per step)
-    "c2": (6, 1024, 64, 100_000),
-    "c3": (8, 4096, 64, 10_000),
-    "c1": (4, 32, 64, 10_000),
+    # name: (L, realizations, walkers per realization, sweeps per step, description)
+    "c2": (6, 1024, 64, 100_000, "L=6, 1024 realizations, power-law target a=1 (dE=1), 1e5 sweeps per weight iteration"),
+    "c3": (8, 4096, 64, 10_000, "L=8, 4096 realizations, power-law target (dE=96, alpha=-3.6), 1e4 sweeps per step"),
+    "c1": (4, 32, 64, 10_000, "L=4, 32 realizations, flat target, 1e4 sweeps per weight iteration"),
 }
+PROFILES = {"c2": (1, 1.0, -1.0), "c3": (1, 96.0, -3.6), "c1": (0, 1.0, 0.0)}
+DSEED = 20110856
 
 
-def gaussian_dos_lnw(L: int, K: int, eb: int) -> np.ndarray:
-    """Multicanonical log-weights of a Gaussian approximation of the density of states,
-    ln g(E) ~ N ln 2 - E^2/(6N) (the high-temperature form for 3N bonds): lnW = E^2/(6N)."""
-    N = L ** 3
-    E = eb + 4 * np.arange(K, dtype=np.float64)
-    return E * E / (6.0 * N)
-
-
-def setup(nfm, L, R, W, seed=20110856):
-    b = nfm.Batch([L] * R, [W] * R, disorder_seed=seed, walker_seed=seed + 1, first_real_id=0)
+def setup(nfm, L, R, W, profile):
+    b = nfm.Batch([L] * R, [W] * R, disorder_seed=DSEED, walker_seed=DSEED + 1, first_real_id=0)
     b.init_couplings()
     b.init_spins()
     b.compute_energies()
-    lnw = np.zeros(b.levels_total)
-    klo, ktop = [], []
-    for r in range(R):
-        K, eb = b.levels(r), b.e_base(r)
-        off = b.level_offset(r)
-        lnw[off:off + K] = gaussian_dos_lnw(L, K, eb)
-        k_top = (-eb + 3) // 4
-        k_lo = max(0, (int(-1.85 * L ** 3) - eb) // 4)
-        klo.append(k_lo)
-        ktop.append(k_top)
-    b.set_weights_lnw(lnw, klo, ktop)
-    for r in range(R):
-        b.set_rt_bounds(r, int(-1.6 * L ** 3), 0)
-    return b, lnw, klo, ktop
+    b.rec_init(*profile)
+    return b
 
 
-def _oracle_worker(args):
-    L, seed, rid, walkers, sweeps, thr, row0, e_bot = args
+def _oracle_iteration(args):
+    L, rid, W, sweeps, profile = args
     from oracle import oracle as orc
-    J = orc.couplings(L, seed, rid)
+    rz = orc.make_realization(L, DSEED, rid, DSEED + 1, W)
+    st = orc.recursion_init(rz)
     t0 = time.perf_counter()
-    n = 0
-    for wk in walkers:
-        s = orc.spins(L, seed + 1, rid, wk)
-        w = orc.new_walkers(1, orc.energy(L, J, s))
-        orc.muca_sweeps(L, J, s, w, thr, row0, e_bot, 0, seed + 1, rid, wk, 0, sweeps)
-        n += sweeps * L ** 3
-    return n, time.perf_counter() - t0
+    orc.weight_iterations(rz, st, n_iter=1, n_sweeps=sweeps, profile=profile[0], pl_dE=profile[1],
+                          pl_alpha=profile[2], stop=False)
+    return W * sweeps * L ** 3, time.perf_counter() - t0
 
 
-def cpu_baseline(b, L, lnw, klo, ktop, seconds_target=15.0):
-    """The oracle as it stands, one process per core over disjoint walkers of the same
-    realizations and weights, on a bounded sample (about seconds_target of wall time)."""
-    from oracle import oracle as orc
+def cpu_baseline(L, W, profile, seconds_target=15.0):
+    """The oracle as it stands: one weight iteration (weights, sweeps, update) per realization,
+    one process per core over distinct realizations, on a bounded sample."""
     cores = max(1, min(16, os.cpu_count() or 1))
-    R = min(8, b.n_real)
-    tasks = []
-    probe_sweeps = 20
-    # rate probe on one core to size the sample
-    J = orc.couplings(L, 20110856, 0)
-    K, eb = orc.n_levels(L, J), orc.e_base(L, J)
-    thr, row0 = orc.build_thresholds(K, lnw[b.level_offset(0) + klo[0]:b.level_offset(0) + ktop[0] + 1], klo[0], ktop[0])
-    n, dt = _oracle_worker((L, 20110856, 0, [0], probe_sweeps, thr, row0, int(-1.6 * L ** 3)))
+    n, dt = _oracle_iteration((L, 0, 4, 20, profile))          # rate probe, 4 walkers x 20 sweeps
     per_core = n / dt
-    sweeps = max(10, int(seconds_target * per_core / (L ** 3) / 8))  # 8 walkers per task
-    for r in range(R):
-        J = orc.couplings(L, 20110856, r)
-        K, eb = orc.n_levels(L, J), orc.e_base(L, J)
-        off = b.level_offset(r)
-        thr, row0 = orc.build_thresholds(K, lnw[off + klo[r]:off + ktop[r] + 1], klo[r], ktop[r])
-        for chunk in range(max(1, cores // R)):
-            tasks.append((L, 20110856, r, list(range(chunk * 8, chunk * 8 + 8)), sweeps, thr, row0,
-                          int(-1.6 * L ** 3)))
+    sweeps = max(10, int(seconds_target * per_core / (W * L ** 3)))
+    tasks = [(L, rid, W, sweeps, profile) for rid in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_worker, tasks)
+        res = pool.map(_oracle_iteration, tasks)
     wall = time.perf_counter() - t0
     total = sum(r[0] for r in res)
-    return {"value": total / wall, "unit": "spin-flip attempts/s", "cores": cores, "kind": "oracle",
-            "sample": f"L={L}, {len(tasks)} tasks x 8 walkers x {sweeps} sweeps over {R} realizations "
-                      f"({total:.3g} attempts, {wall:.1f} s wall, {cores} processes)"}
+    return {"value": total / wall, "unit": "attempts/s", "cores": cores, "kind": "oracle",
+            "sample": f"L={L}: {cores} realizations x {W} walkers, one weight iteration of {sweeps} sweeps each "
+                      f"({total:.3g} attempts in {wall:.1f} s wall, {cores} processes)"}
 
 
 def main():
@@ -124,43 +90,49 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the config's)")
+    ap.add_argument("--walkers", type=int, default=0, help="walkers per realization (default: the config's)")
+    ap.add_argument("--speculate", type=int, default=-1, choices=[-1, 0, 1],
+                    help="speculative table lookups: -1 automatic, 0 off, 1 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(realizations are independent: shard them across processes, one per GPU)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported here "
+              f"(realizations are independent: one process per GPU would take a range of them)", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2011_08560_amd import nfm
 
-    L, R, W, S = CONFIGS[args.config]
-    if args.sweeps:
-        S = args.sweeps
-    b, lnw, klo, ktop = setup(nfm, L, R, W)
+    L, R, W, S, desc = CONFIGS[args.config]
+    S = args.sweeps or S
+    W = args.walkers or W
+    profile = PROFILES[args.config]
+    b = setup(nfm, L, R, W, profile)
+    b.set_tuning(speculate=args.speculate)
     stream = torch.cuda.current_stream()
     attempts_per_step = R * W * S * L ** 3
-    launches_per_step = math.ceil(S / 1024)
+    launches_per_step = math.ceil(S / SWEEPS_PER_LAUNCH)
 
     for _ in range(args.warmup):
         b.run_sweeps(S)
-        b.read_realizations()
+        b.rec_update(0.5)
     torch.cuda.synchronize()
     trips0 = int(b.read_realizations()["rt_count"].sum())
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    info = None
     for k in range(args.steps):
         ev[k][0].record(stream)
         b.run_sweeps(S)
         ev[k][1].record(stream)
-        b.read_realizations()
+        info = b.rec_update(0.5)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     trips = int(b.read_realizations()["rt_count"].sum()) - trips0
-    kernel_ms = sum(s.elapsed_time(e) for s, e in ev)
-    avg_launch_s = kernel_ms / 1e3 / (args.steps * launches_per_step)
+    sweep_ms = sum(s.elapsed_time(e) for s, e in ev)
+    avg_launch_s = sweep_ms / 1e3 / (args.steps * launches_per_step)
     attempts_per_launch = attempts_per_step / launches_per_step
     achieved = ALG_OPS_PER_ATTEMPT * attempts_per_launch / avg_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
@@ -178,21 +150,21 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 3D +-J EA L={L}, {R} realizations x {W} walkers, "
-                               f"{S} multicanonical sweeps per step, checkerboard single-spin Metropolis",
-                   "L": L, "realizations": R, "walkers_per_realization": W, "sweeps_per_step": S},
+        "config": {"workload": f"{args.config}: 3D +-J EA {desc}; one step = sweeps + device weight update",
+                   "L": L, "realizations": R, "walkers_per_realization": W, "sweeps_per_step": S,
+                   "profile": {"kind": ["flat", "power", "invk"][profile[0]], "dE": profile[1], "alpha": profile[2]}},
         "round_trips_per_s": trips / wall,
-        "kernel_attempts_per_s": attempts_per_step * args.steps / (kernel_ms / 1e3),
+        "weight_iterations": {"done": int(info["iterations"].max()),
+                              "converged_fraction": float(info["converged"].mean()),
+                              "median_flatness": float(np.median(info["flatness"]))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": f"k_muca_sweeps<{L}>", "avg_launch_ms": avg_launch_s * 1e3,
-                     "alg_ops_per_attempt": ALG_OPS_PER_ATTEMPT},
+                     "alg_ops_per_attempt": ALG_OPS_PER_ATTEMPT, "speculate": args.speculate},
     }
     b.close()
     if not args.no_cpu_baseline:
-        b2, lnw2, klo2, ktop2 = setup(nfm, L, min(R, 8), W)
-        line["cpu_baseline"] = cpu_baseline(b2, L, lnw2, klo2, ktop2)
-        b2.close()
+        line["cpu_baseline"] = cpu_baseline(L, W, profile)
     print(json.dumps(line))
 
 

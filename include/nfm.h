@@ -238,6 +238,20 @@ nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const dou
                              const double* lnP, const double* lnW, const uint8_t* visited,
                              const nfm_rec_info* info);
 
+/* Launch tuning of nfm_run_sweeps (results do not depend on it: the random stream is indexed
+ * by sweep, site and walker, and all accumulation is integer).
+ *   speculate: -1 automatic, 0 off, 1 on. With speculation each attempt also loads the next
+ *     site's two candidate thresholds (accepted / rejected) before its own decision resolves,
+ *     which shortens a walker's serial chain at the cost of a second table read; automatic
+ *     turns it on when a launch has fewer than 8 waves per compute unit.
+ *   sweeps_per_launch: sweeps per kernel launch (0 = 1024). */
+typedef struct {
+  int32_t speculate;
+  int32_t sweeps_per_launch;
+} nfm_tuning;
+nfm_status nfm_set_tuning(nfm_ctx* ctx, const nfm_tuning* tuning);
+nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
+
 nfm_status nfm_sync(nfm_ctx* ctx);
 
 #ifdef __cplusplus

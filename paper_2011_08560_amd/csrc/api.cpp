@@ -106,6 +106,9 @@ struct nfm_ctx {
   int trace_cap = 0;
   uint64_t sweeps = 0, trace_t0 = 0;
   bool couplings = false;
+  int speculate = -1;                      // -1 auto, 0 off, 1 on
+  uint32_t sweeps_per_launch = kMaxSweepsPerLaunch;
+  int n_cu = 256;
   std::vector<RealInfo> reals;
   // waves grouped by L
   std::vector<int> group_L;
@@ -297,6 +300,9 @@ nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_works
       delete c;
       return NFM_EDEVICE;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+      c->n_cu = ncu;
     nfm_status st = NFM_OK;
     if (hipMemcpyAsync(c->d_waves(), wr.data(), 4 * wr.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->d_waves() + l.total_waves, wwl.data(), 4 * wwl.size(), hipMemcpyHostToDevice,
@@ -509,7 +515,7 @@ nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
     return fail(c, NFM_ERANGE, "run_sweeps: the sweep counter must stay below 2^32");
   uint64_t done = 0;
   while (done < n_sweeps) {
-    const uint32_t chunk = (uint32_t)std::min<uint64_t>(kMaxSweepsPerLaunch, n_sweeps - done);
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(c->sweeps_per_launch, n_sweeps - done);
     for (size_t g = 0; g < c->group_L.size(); ++g) {
       const int L = c->group_L[g];
       int lds_rows = 1;
@@ -530,7 +536,10 @@ nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
       a.t0 = c->sweeps + done;
       a.n_sweeps = chunk;
       a.walker_seed = c->walker_seed;
-      hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, c->stream);
+      // Speculative lookups shorten each walker's serial chain; they pay off when there are
+      // too few waves per SIMD to hide the LDS latency with other waves.
+      const bool spec = c->speculate >= 0 ? c->speculate == 1 : c->group_n_waves[g] < 2 * 4 * (int64_t)c->n_cu;
+      hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, spec, c->stream);
       if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
     }
     done += chunk;
@@ -723,6 +732,23 @@ nfm_status nfm_rec_set_state(nfm_ctx* c, int32_t r, const double* b, const doubl
   NFM_HIP(c, hipMemcpyAsync(c->d_recs() + r, info, sizeof(nfm_rec_info), hipMemcpyHostToDevice, c->stream));
   NFM_HIP(c, hipStreamSynchronize(c->stream));
   c->rec_ready = true;
+  return NFM_OK;
+}
+
+
+nfm_status nfm_set_tuning(nfm_ctx* c, const nfm_tuning* t) {
+  if (!c || !t) return NFM_EINVAL;
+  if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0)
+    return fail(c, NFM_EINVAL, "set_tuning: speculate in {-1,0,1}, sweeps_per_launch >= 0");
+  c->speculate = t->speculate;
+  c->sweeps_per_launch = t->sweeps_per_launch == 0 ? kMaxSweepsPerLaunch : (uint32_t)t->sweeps_per_launch;
+  return NFM_OK;
+}
+
+nfm_status nfm_get_tuning(const nfm_ctx* c, nfm_tuning* t) {
+  if (!c || !t) return NFM_EINVAL;
+  t->speculate = c->speculate;
+  t->sweeps_per_launch = (int32_t)c->sweeps_per_launch;
   return NFM_OK;
 }
 

@@ -42,7 +42,7 @@ hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, Rec
                                  int profile, double pl_dE, double pl_alpha, hipStream_t s);
 
 // sweep.hip
-hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s);
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s);
 bool sweep_supported(int L);
 
 }  // namespace nfm

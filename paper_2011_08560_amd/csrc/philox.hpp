@@ -42,4 +42,42 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
   return r;
 }
 
+// The same generator with the ten round keys precomputed in vector registers.
+struct PhiloxKeysV {
+  uint32_t k0[10], k1[10];
+};
+
+__device__ __forceinline__ PhiloxKeysV philox_round_keys_v(uint32_t k0, uint32_t k1) {
+  PhiloxKeysV kv;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t a = k0 + (uint32_t)r * 0x9E3779B9u, b = k1 + (uint32_t)r * 0xBB67AE85u;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(kv.k0[r]) : "s"(a));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(kv.k1[r]) : "s"(b));
+  }
+  return kv;
+}
+
+__device__ __forceinline__ u32x4 philox4x32_10_vk(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                  const PhiloxKeysV& kv) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)M0 * c0;
+    const uint64_t p1 = (uint64_t)M1 * c2;
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, kv.k0[round], 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, kv.k1[round], 0x96);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  u32x4 r;
+  r.v[0] = c0;
+  r.v[1] = c1;
+  r.v[2] = c2;
+  r.v[3] = c3;
+  return r;
+}
+
 }  // namespace nfm

@@ -111,7 +111,7 @@ __device__ __forceinline__ void track_attempt(Track& tr, int B, uint64_t tau, in
   }
 }
 
-template <int L>
+template <int L, bool SPEC>
 __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
   using G = Geo<L>;
   using PW = typename G::PW;
@@ -175,6 +175,9 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
   Window win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
 
   const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
+  // Round keys in VGPRs: uniform values, but keeping them out of the scalar file leaves room for
+  // the per-plane coupling words and constants without spilling scalar registers.
+  PhiloxKeysV kv = philox_round_keys_v(key0, key1);
   const uint32_t ctr3 = ((uint32_t)wl << 8) | kTagAcc;
   const uint32_t* jreal = A.jk + RI.jk_off;
 
@@ -246,39 +249,67 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
 
         const uint32_t ctr0 = (uint32_t)(c * L + z) << 8;
         const uint64_t tau_blk = tau0 + (uint64_t)(c * (N / 2) + z * Q);
+        // m & 7 of site q in bits 2..4 (sign at bit 4) of a product high word
+        auto gather = [&](int q) __attribute__((always_inline)) -> uint32_t {
+          const int y = q / G::H, j = q % G::H;
+          const int p = y * G::F + j, g8 = p >> 3, bb = p & 7;
+          // (2^26 + 2^19 + 2^12) >> bb: eight distinct constants in all
+          return __umulhi(V[g8] & (0x01010100u << bb), 0x04081000u >> bb);
+        };
+        auto lookup = [&](uint32_t hi, int Bv) __attribute__((always_inline)) -> uint32_t {
+          int R;
+          asm("v_med3_i32 %0, %1, 0, %2" : "=v"(R) : "v"(Bv), "s"(Bmax));
+          const uint32_t addr = (hi & 0x1cu) | (uint32_t)R;      // R is a multiple of 32
+          return *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr;
+        };
+        int Bq[4];
+        uint32_t hi_cur = gather(0);
+        uint32_t th_cur = lookup(hi_cur, B);
 #pragma unroll
         for (int g = 0; g < (Q + 3) / 4; ++g) {
-          const u32x4 rnd = philox4x32_10(ctr0 | (uint32_t)g, (uint32_t)t, real_id, ctr3, key0, key1);
-          int Bq[4];
+          const u32x4 rnd = philox4x32_10_vk(ctr0 | (uint32_t)g, (uint32_t)t, real_id, ctr3, kv);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int q = 4 * g + i;
-            Bq[i] = B;
-            if (q >= Q) continue;
+            if (q >= Q) break;
             const int y = q / G::H, j = q % G::H;
-            const int p = y * G::F + j, w = p >> 5, b = p & 31, g8 = p >> 3, bb = p & 7;
-            uint32_t cmul;  // per-site constant kept out of loop-invariant hoisting
-            asm volatile("s_mov_b32 %0, %1" : "=s"(cmul) : "i"((1u << (26 - bb)) + (1u << (19 - bb)) + (1u << (12 - bb))));
-            const uint32_t hi = __umulhi(V[g8] & (0x01010100u << bb), cmul);
-            int R;
-            asm("v_med3_i32 %0, %1, 0, %2" : "=v"(R) : "v"(B), "s"(Bmax));
-            const uint32_t addr = (hi & 0x1cu) | (uint32_t)R;      // R is a multiple of 32
-            const uint32_t th = *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr;
-            const uint32_t rv = min(rnd.v[i], 0xFFFFFFFEu);
-            if (rv < th) {
-              Cw[w] ^= 1u << b;
-              B += __builtin_amdgcn_sbfe((int)hi, 2, 3) * 32;             // 32 m
+            const int p = y * G::F + j, w = p >> 5, b = p & 31;
+            const int Bacc = B + __builtin_amdgcn_sbfe((int)hi_cur, 2, 3) * 32;   // B after acceptance
+            uint32_t hi_next = 0, th_rej = 0, th_acc = 0;
+            if (SPEC && q + 1 < Q) {
+              // both candidate thresholds of the next site, before this decision resolves
+              hi_next = gather(q + 1);
+              th_rej = lookup(hi_next, B);
+              th_acc = lookup(hi_next, Bacc);
+            }
+            const bool acc = min(rnd.v[i], 0xFFFFFFFEu) < th_cur;
+            if (acc) Cw[w] ^= 1u << b;
+            B = acc ? Bacc : B;
+            if (q + 1 < Q) {
+              if (SPEC) {
+                th_cur = acc ? th_acc : th_rej;
+                hi_cur = hi_next;
+              } else {
+                hi_cur = gather(q + 1);
+                th_cur = lookup(hi_cur, B);
+              }
             }
             Bq[i] = B;
           }
-          // Did any attempt of the group leave the window? Then replay the group exactly.
-          const int bmin = min(min(Bq[0], Bq[1]), min(Bq[2], Bq[3]));
-          const int bmax = max(max(Bq[0], Bq[1]), max(Bq[2], Bq[3]));
+          // Did an attempt of this group leave the window? Then replay the group exactly.
+          const int last = (4 * g + 3 < Q) ? 3 : (Q - 1) - 4 * g;
+          int bmin = Bq[0], bmax = Bq[0];
+#pragma unroll
+          for (int k = 1; k < 4; ++k) {
+            if (k > last) break;
+            bmin = min(bmin, Bq[k]);
+            bmax = max(bmax, Bq[k]);
+          }
           if (bmin < win.lo || bmax > win.hi) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int q = 4 * g + i;
-              if (q < Q) track_attempt(tr, Bq[i], tau_blk + (uint64_t)q, e_base, row0, e_bot, e_top);
+            for (int k = 0; k < 4; ++k) {
+              if (k > last) break;
+              track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g + k), e_base, row0, e_bot, e_top);
             }
             win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
           }
@@ -313,33 +344,38 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
   A.ws.t_last[gw] = tr.t_last;
 }
 
-template <int L>
-static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s) {
+template <int L, bool SPEC>
+static hipError_t launch_LS(const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s) {
   // The kernel addresses its dynamic LDS block from address 0, which is only valid
   // when the compiler placed nothing else in LDS.
   static int checked = 0;
   if (!checked) {
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_muca_sweeps<L>));
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_muca_sweeps<L, SPEC>));
     if (e != hipSuccess) return e;
     if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     checked = 1;
   }
   const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_muca_sweeps<L>, dim3(n_waves), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_muca_sweeps<L, SPEC>), dim3(n_waves), dim3(64), lds, s, a);
   return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s) {
+  return spec ? launch_LS<L, true>(a, n_waves, lds_rows, s) : launch_LS<L, false>(a, n_waves, lds_rows, s);
 }
 
 bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
 
-hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s) {
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s) {
   switch (L) {
-    case 2: return launch_L<2>(a, n_waves, lds_rows, s);
-    case 4: return launch_L<4>(a, n_waves, lds_rows, s);
-    case 6: return launch_L<6>(a, n_waves, lds_rows, s);
-    case 8: return launch_L<8>(a, n_waves, lds_rows, s);
-    case 10: return launch_L<10>(a, n_waves, lds_rows, s);
-    case 12: return launch_L<12>(a, n_waves, lds_rows, s);
+    case 2: return launch_L<2>(a, n_waves, lds_rows, spec, s);
+    case 4: return launch_L<4>(a, n_waves, lds_rows, spec, s);
+    case 6: return launch_L<6>(a, n_waves, lds_rows, spec, s);
+    case 8: return launch_L<8>(a, n_waves, lds_rows, spec, s);
+    case 10: return launch_L<10>(a, n_waves, lds_rows, spec, s);
+    case 12: return launch_L<12>(a, n_waves, lds_rows, spec, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -93,6 +93,8 @@ def lib():
         "nfm_rec_read_info": (i32, [vp, vp]),
         "nfm_rec_get_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "nfm_rec_set_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
+        "nfm_set_tuning": (i32, [vp, vp]),
+        "nfm_get_tuning": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -368,3 +370,13 @@ class Batch:
         self._check(self._lib.nfm_rec_set_state(self.ctx, r, arr[0].ctypes.data, arr[1].ctypes.data,
                                                 arr[2].ctypes.data, arr[3].ctypes.data, vis.ctypes.data,
                                                 info.ctypes.data), "rec_set_state")
+
+    # launch tuning
+    def set_tuning(self, speculate: int = -1, sweeps_per_launch: int = 0):
+        t = np.array([speculate, sweeps_per_launch], np.int32)
+        self._check(self._lib.nfm_set_tuning(self.ctx, t.ctypes.data), "set_tuning")
+
+    def get_tuning(self):
+        t = np.zeros(2, np.int32)
+        self._check(self._lib.nfm_get_tuning(self.ctx, t.ctypes.data), "get_tuning")
+        return int(t[0]), int(t[1])
