@@ -421,3 +421,118 @@ void orc_rec_update(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_min_s
   *flatness = (n > 0 && sum > 0.0) ? mn / (sum / (double)n) : 0.0;
   *k_lo_new = k_lo;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Parallel tempering (Sec. II, Eq. (8)): M copies of the system at temperatures
+ * T_0 < ... < T_{M-1}, each updated by canonical Metropolis, and exchanges of the
+ * configurations of neighbouring temperatures.
+ *
+ * Metropolis table, one row per temperature slot in the layout of the multicanonical
+ * tables (u = 0..6, pad): the step m = 3 - u changes E by 4m, accepted with
+ * x = exp(-(1/T) (4m)) for m > 0 and always for m <= 0.                          */
+void orc_pt_metro_table(int32_t M, const double* T, uint32_t* thr) {
+  for (int32_t s = 0; s < M; ++s) {
+    double beta = 1.0 / T[s];
+    for (int32_t u = 0; u < 8; ++u) {
+      uint32_t t = 0;
+      if (u <= 6) {
+        int32_t m = 3 - u;
+        t = m <= 0 ? 0xFFFFFFFFu : quantize(exp(-beta * (double)(4 * m)));
+      }
+      thr[s * 8 + u] = t;
+    }
+  }
+}
+
+/* Exchange table: for the pair of slots (s, s+1) and d = (E_{s+1} - E_s)/4 >= 1 the
+ * exchange is accepted with x = exp((1/T_{s+1} - 1/T_s) (4d)) (Eq. (8)); entry
+ * [s][d-1] holds its threshold. Exchanges with d <= 0 always succeed. D is the
+ * smallest d at which every pair's threshold is 0 (so that larger d may be clamped
+ * to D), but at most d_cap. Returns D; thr may be NULL to query it.              */
+int32_t orc_pt_swap_table(int32_t M, const double* T, int32_t d_cap, uint32_t* thr) {
+  int32_t D = d_cap;
+  for (int32_t d = 1; d <= d_cap; ++d) {
+    int32_t all_zero = 1;
+    for (int32_t s = 0; s + 1 < M; ++s) {
+      double db = 1.0 / T[s + 1] - 1.0 / T[s];
+      if (quantize(exp(db * (double)(4 * d))) != 0u) all_zero = 0;
+    }
+    if (all_zero) {
+      D = d;
+      break;
+    }
+  }
+  if (thr) {
+    for (int32_t s = 0; s + 1 < M; ++s) {
+      double db = 1.0 / T[s + 1] - 1.0 / T[s];
+      for (int32_t d = 1; d <= D; ++d) thr[s * D + (d - 1)] = quantize(exp(db * (double)(4 * d)));
+    }
+  }
+  return D;
+}
+
+/* One set of M configurations of one realization. Configuration c (walker index
+ * set*M + c of the realization) holds spins S[c*N .. c*N+N-1], bookkeeping w[c] and
+ * temperature slot slot[c]. Each sweep t: every configuration, in order c = 0..M-1,
+ * makes one checkerboard sweep of Metropolis attempts at T_slot (acceptance words as
+ * in the multicanonical sweep with tag TAG_PT); then each configuration's energy is
+ * tracked with stamp (t+1) N (round trips between e_bot and e_top, Sec. III); then
+ * the pairs of slots (s, s+1) with s = t (mod 2) try an exchange, accepted when
+ * thr == 0xFFFFFFFF or r < thr, r = output[s & 3] of counter
+ * (s >> 2, t, real_id, (set << 8) | TAG_SWAP) under the walker seed.               */
+int32_t orc_pt_sweeps(int32_t L, const int8_t* J, int32_t M, int8_t* S, orc_walker* w, int32_t* slot,
+                      const uint32_t* metro, const uint32_t* swap, int32_t D, int32_t e_bot, int32_t e_top,
+                      uint64_t walker_seed, uint32_t real_id, uint32_t set, uint64_t t0, uint64_t n_sweeps,
+                      uint64_t* swap_acc, int32_t* trace, int32_t check_energy) {
+  int32_t N = L * L * L;
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  uint32_t* slot_ctr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
+  int32_t* slot_which = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t* at = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+  if (!order || !slot_ctr || !slot_which || !at) {
+    free(order); free(slot_ctr); free(slot_which); free(at);
+    return -2;
+  }
+  orc_sweep_order(L, order);
+  for (int32_t i = 0; i < N; ++i) site_rng_slot(L, i, &slot_ctr[i], &slot_which[i]);
+  int32_t status = 0;
+  for (uint64_t t = t0; t < t0 + n_sweeps; ++t) {
+    for (int32_t c = 0; c < M; ++c) {
+      int8_t* Sc = S + (size_t)c * (size_t)N;
+      uint32_t walker = set * (uint32_t)M + (uint32_t)c;
+      for (int32_t a = 0; a < N; ++a) {
+        int32_t i = order[a];
+        int32_t u = orc_unsatisfied(L, J, Sc, i);
+        uint32_t th = metro[slot[c] * 8 + u];
+        uint32_t r = philox_word(slot_ctr[i], (uint32_t)t, real_id, (walker << 8) | ORC_TAG_PT,
+                                 walker_seed, slot_which[i]);
+        if (th == 0xFFFFFFFFu || r < th) {
+          Sc[i] = (int8_t)(-Sc[i]);
+          w[c].E += 12 - 4 * u;
+        }
+      }
+      if (check_energy && w[c].E != orc_energy(L, J, Sc)) status = -1;
+      orc_track(&w[c], w[c].E, e_bot, e_top, (t + 1u) * (uint64_t)N);
+      if (trace) trace[(size_t)c * n_sweeps + (t - t0)] = w[c].E;
+    }
+    for (int32_t c = 0; c < M; ++c) at[slot[c]] = c;
+    for (int32_t s = (int32_t)(t & 1u); s + 1 < M; s += 2) {
+      int32_t lo = at[s], hi = at[s + 1];
+      int32_t d = (w[hi].E - w[lo].E) / 4;
+      uint32_t th = 0xFFFFFFFFu;
+      if (d > 0) th = swap[s * D + (d < D ? d : D) - 1];
+      uint32_t r = philox_word((uint32_t)(s >> 2), (uint32_t)t, real_id, (set << 8) | ORC_TAG_SWAP,
+                               walker_seed, s & 3);
+      if (th == 0xFFFFFFFFu || r < th) {
+        slot[lo] = s + 1;
+        slot[hi] = s;
+        if (swap_acc) swap_acc[s] += 1u;
+      }
+    }
+  }
+  free(order);
+  free(slot_ctr);
+  free(slot_which);
+  free(at);
+  return status;
+}

@@ -92,6 +92,13 @@ def lib():
         L.orc_rec_update.argtypes = [i32, i32, i32, i32, P(np.float64), P(np.float64), P(np.uint64),
                                      P(np.float64), P(np.float64), P(np.uint8), C.POINTER(i32),
                                      C.POINTER(dbl)]
+        L.orc_pt_metro_table.argtypes = [i32, P(np.float64), P(np.uint32)]
+        L.orc_pt_swap_table.argtypes = [i32, P(np.float64), i32, C.c_void_p]
+        L.orc_pt_swap_table.restype = i32
+        L.orc_pt_sweeps.argtypes = [i32, P(np.int8), i32, P(np.int8), C.c_void_p, P(np.int32), P(np.uint32),
+                                    P(np.uint32), i32, i32, i32, u64, u32, u32, u64, u64, C.c_void_p,
+                                    C.c_void_p, i32]
+        L.orc_pt_sweeps.restype = i32
         _lib = L
     return _lib
 
@@ -318,3 +325,94 @@ def production_weights(rz: Realization, st: RecursionState, kind: str, pl_dE=96.
     prof = {"flat": PROFILE_FLAT, "power": PROFILE_POWER, "invk": PROFILE_INVK}[kind]
     S, lnP, lnW = rec_weights(rz.K, rz.eb, st.k_lo, st.k_top, prof, pl_dE, pl_alpha, st.b)
     return lnW
+
+
+# --------------------------------------------------------------------------- parallel tempering
+
+def pt_temperatures(M: int, t_min: float = 0.2, t_max: float = 2.0) -> np.ndarray:
+    """Geometric temperature ladder T_s = t_min (t_max/t_min)^(s/(M-1))."""
+    return np.array([t_min * (t_max / t_min) ** (s / (M - 1)) for s in range(M)], np.float64)
+
+
+def pt_metro_table(T) -> np.ndarray:
+    T = np.ascontiguousarray(T, np.float64)
+    thr = np.zeros(len(T) * 8, np.uint32)
+    lib().orc_pt_metro_table(len(T), T, thr)
+    return thr.reshape(len(T), 8)
+
+
+def pt_swap_table(T, d_cap: int) -> np.ndarray:
+    """(M-1) x D exchange thresholds, entry [s][d-1] for d = (E_{s+1} - E_s)/4."""
+    T = np.ascontiguousarray(T, np.float64)
+    D = lib().orc_pt_swap_table(len(T), T, d_cap, None)
+    thr = np.zeros((len(T) - 1) * D, np.uint32)
+    lib().orc_pt_swap_table(len(T), T, d_cap, thr.ctypes.data)
+    return thr.reshape(len(T) - 1, D)
+
+
+@dataclass
+class PTSet:
+    """One parallel-tempering set: M configurations of one realization."""
+    L: int
+    J: np.ndarray
+    real_id: int
+    walker_seed: int
+    set_index: int
+    S: np.ndarray          # int8 [M, N]
+    w: np.ndarray          # WALKER_DTYPE [M]
+    slot: np.ndarray       # int32 [M], temperature slot of each configuration
+    t: int = 0
+
+
+def make_pt_set(L, disorder_seed, real_id, walker_seed, M, set_index=0) -> PTSet:
+    """Configurations start from the spins of walkers set*M .. set*M+M-1; configuration c
+    starts at slot c."""
+    J = couplings(L, disorder_seed, real_id)
+    ws = [set_index * M + c for c in range(M)]
+    S = np.stack([spins(L, walker_seed, real_id, w) for w in ws])
+    E0 = np.array([energy(L, J, S[c]) for c in range(M)], np.int32)
+    return PTSet(L, J, real_id, walker_seed, set_index, S, new_walkers(M, E0), np.arange(M, dtype=np.int32))
+
+
+def pt_sweeps(ps: PTSet, metro, swap, e_bot, e_top, n_sweeps, swap_acc=None, trace=False, check_energy=False):
+    """Advance a PT set by n_sweeps in place; returns the traces (M x n_sweeps) or None."""
+    M = ps.S.shape[0]
+    metro = np.ascontiguousarray(metro, np.uint32).reshape(-1)
+    swap = np.ascontiguousarray(swap, np.uint32)
+    D = swap.shape[1]
+    tr = np.zeros((M, n_sweeps), np.int32) if trace else None
+    S = np.ascontiguousarray(ps.S)
+    rc = lib().orc_pt_sweeps(ps.L, ps.J, M, S, ps.w.ctypes.data, ps.slot, metro, swap.reshape(-1), D,
+                             e_bot, e_top, ps.walker_seed, ps.real_id, ps.set_index, ps.t, n_sweeps,
+                             None if swap_acc is None else swap_acc.ctypes.data,
+                             None if tr is None else tr.ctypes.data, 1 if check_energy else 0)
+    if rc == -1:
+        raise AssertionError("incremental energy disagrees with recomputation")
+    if rc != 0:
+        raise RuntimeError("oracle PT sweep failed")
+    ps.S = S
+    ps.t += n_sweeps
+    return tr
+
+
+# --------------------------------------------------------------------------- round-trip statistics
+
+def rt_tau(rt_count, t_first, t_last, N: int, min_trips: int = 1):
+    """Round-trip time of one realization (Sec. III), pooled over its walkers: the summed
+    time of completed trips, from each walker's first arrival at the top to its last
+    completed trip, over the number of trips, in sweeps (attempts / N). Returns
+    (tau, trips, censored); censored (tau = nan) when fewer than min_trips trips."""
+    rt_count = np.asarray(rt_count, np.uint64)
+    done = rt_count > 0
+    trips = int(rt_count.sum())
+    time = int((np.asarray(t_last, np.uint64)[done] - np.asarray(t_first, np.uint64)[done]).sum())
+    if trips < max(1, min_trips):
+        return float("nan"), trips, True
+    return time / trips / N, trips, False
+
+
+def rt_population(taus):
+    """tau_pop: mean of the uncensored per-realization round-trip times."""
+    t = np.asarray(taus, np.float64)
+    t = t[~np.isnan(t)]
+    return float(t.sum() / len(t)) if len(t) else float("nan")
