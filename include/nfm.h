@@ -254,6 +254,55 @@ nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
 
 nfm_status nfm_sync(nfm_ctx* ctx);
 
+/* ---------------------------------------------------------------------------------------
+ * Parallel tempering (Sec. II, Eq. (8)), the baseline the paper compares against. The
+ * walkers of each realization form walkers/M sets of M configurations (walker index
+ * set*M + c); each configuration sits at one temperature slot of the set, slots being a
+ * permutation of 0..M-1. One PT sweep: every configuration makes one checkerboard sweep of
+ * canonical Metropolis attempts at its slot's temperature (random words as in
+ * nfm_run_sweeps, tag 4 instead of 1); then its energy goes through the round-trip
+ * bookkeeping (bounds of nfm_set_rt_bounds; stamp (t+1) N, so round-trip times come out in
+ * PT sweeps) and the trace; then the slot pairs (s, s+1) with s = t (mod 2) try an
+ * exchange with probability min(1, exp((1/T_{s+1} - 1/T_s)(E_{s+1} - E_s))), taking
+ * output[s & 3] of Philox counter (s >> 2, t, real_id, (set << 8) | 5) under the walker seed.
+ * Energies are tracked per attempt, so nfm_compute_energies must have run first.
+ *
+ * nfm_pt_init: M a power of two in [2, 64]; host_temps[M] strictly increasing, > 0. Builds
+ *   on the host (FP64) the Metropolis table (M rows x 8 words in the layout of the
+ *   multicanonical tables: entry u = 0..6 is the threshold of the step m = 3 - u,
+ *   floor(exp(-(1/T)(4m)) 2^32) for m > 0, 0xFFFFFFFF for m <= 0, entry 7 = 0) and the exchange
+ *   table ((M-1) rows x D: entry [s][d-1] = floor(exp((1/T_{s+1} - 1/T_s)(4d)) 2^32), D the
+ *   first d at which every row is 0, at most 3N/2 + 1; larger d clamp to D), puts walker
+ *   set*M + c at slot c and clears the exchange counters. Round-trip state is left as is
+ *   (see nfm_reset_round_trips). EINVAL on bad M or temperatures, ESTATE without couplings. */
+nfm_status nfm_pt_init(nfm_ctx* ctx, int32_t M, const double* host_temps);
+/* Inject / read the tables (same layouts; D in [1, 3N/2 + 1] of the largest N). */
+nfm_status nfm_pt_set_tables(nfm_ctx* ctx, const uint32_t* host_metro, const uint32_t* host_swap, int32_t D);
+nfm_status nfm_pt_get_tables(nfm_ctx* ctx, uint32_t* host_metro, uint32_t* host_swap, int32_t* M, int32_t* D);
+/* Run n PT sweeps of every walker (asynchronous on the stream; advances the sweep counter). */
+nfm_status nfm_pt_run_sweeps(nfm_ctx* ctx, uint64_t n_sweeps);
+/* Slots of all walkers (int32, nfm_n_walkers() entries); set_slots checks that each set holds a
+ * permutation of 0..M-1. */
+nfm_status nfm_pt_read_slots(nfm_ctx* ctx, int32_t* host_slots);
+nfm_status nfm_pt_set_slots(nfm_ctx* ctx, const int32_t* host_slots);
+/* Accepted exchanges since nfm_pt_init: uint64 [n_walkers / M][M - 1], entry [g][s] for the
+ * pair (s, s+1) of global set g = walker / M. */
+nfm_status nfm_pt_read_exchanges(nfm_ctx* ctx, uint64_t* host_acc);
+
+/* ---------------------------------------------------------------------------------------
+ * Round-trip statistics (Sec. III). For realization r: tau_r = (sum over walkers with trips of
+ * t_last - t_first) / (trips) / N, in sweeps (the stamps count attempts), NaN when it has fewer
+ * than max(1, min_trips) trips (censored). tau_pop = mean of the uncensored tau_r of the range.
+ * host_tau (may be NULL) receives count doubles. Synchronizes. */
+typedef struct {
+  double tau_pop;      /* NaN if every realization of the range is censored */
+  uint64_t trips;      /* completed round trips in the range */
+  int32_t n_used;      /* uncensored realizations */
+  int32_t n_censored;
+} nfm_rt_summary;
+nfm_status nfm_rt_stats(nfm_ctx* ctx, int32_t r0, int32_t count, uint64_t min_trips, double* host_tau,
+                        nfm_rt_summary* host_summary);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,6 +26,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t reals, waves, jabi, jk, spins, ws_i32, ws_u64, tables, hist, lnw, klo, ktop, trace, rstats, staging, total;
   size_t recs, rec_f64, rec_vis;
+  size_t pt_slot, pt_acc, pt_metro, pt_swap, rt_tau, rt_sum;
+  int32_t pt_dcap;            // exchange-table width capacity: max over the batch of 3N/2 + 1
   int64_t total_walkers, total_waves, levels_total, jabi_words, jk_words, spin_words, table_words;
   size_t staging_bytes;
 };
@@ -62,6 +65,7 @@ bool make_layout(const nfm_batch_desc* d, Layout* lay, std::string* why) {
     l.spin_words += (int64_t)W * nfm::walker_words(L);
     l.table_words += (int64_t)nfm::level_capacity(N) * 8;
     max_stage = std::max(max_stage, (size_t)W * N);
+    l.pt_dcap = std::max<int32_t>(l.pt_dcap, 3 * N / 2 + 1);
   }
   max_stage = std::max(max_stage, (size_t)l.jabi_words * 4);
   l.staging_bytes = max_stage;
@@ -89,6 +93,12 @@ bool make_layout(const nfm_batch_desc* d, Layout* lay, std::string* why) {
   l.recs = take(sizeof(nfm::RecInfo) * d->n_real);
   l.rec_f64 = take(8 * 5 * (size_t)l.levels_total);
   l.rec_vis = take((size_t)l.levels_total);
+  l.pt_slot = take(4 * (size_t)l.total_walkers);
+  l.pt_acc = take(8 * (size_t)l.total_walkers);
+  l.pt_metro = take(4 * 8 * (size_t)nfm::kMaxReplicas);
+  l.pt_swap = take(4 * (size_t)(nfm::kMaxReplicas - 1) * (size_t)l.pt_dcap);
+  l.rt_tau = take(8 * (size_t)d->n_real);
+  l.rt_sum = take(sizeof(nfm::RtSummaryDev));
   l.total = off;
   *lay = l;
   return true;
@@ -142,6 +152,11 @@ struct nfm_ctx {
     return a;
   }
   bool rec_ready = false;
+  int pt_M = 0, pt_D = 0;                  // parallel tempering: slots per set, exchange-table width
+  int32_t* d_pt_slot() { return (int32_t*)(ws + lay.pt_slot); }
+  uint64_t* d_pt_acc() { return (uint64_t*)(ws + lay.pt_acc); }
+  uint32_t* d_pt_metro() { return (uint32_t*)(ws + lay.pt_metro); }
+  uint32_t* d_pt_swap() { return (uint32_t*)(ws + lay.pt_swap); }
   nfm::WalkerState walker_state() {
     nfm::WalkerState s;
     const int64_t W = lay.total_walkers;
@@ -749,6 +764,192 @@ nfm_status nfm_get_tuning(const nfm_ctx* c, nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
   t->speculate = c->speculate;
   t->sweeps_per_launch = (int32_t)c->sweeps_per_launch;
+  return NFM_OK;
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Parallel tempering (Sec. II, Eq. (8)).
+
+static uint32_t pt_quantize(double x) { return x >= 1.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(std::ldexp(x, 32)); }
+
+static bool pt_valid_M(int M) { return M >= 2 && M <= nfm::kMaxReplicas && (M & (M - 1)) == 0; }
+
+nfm_status nfm_pt_init(nfm_ctx* c, int32_t M, const double* host_temps) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "pt_init: couplings not set");
+  if (!pt_valid_M(M)) return fail(c, NFM_EINVAL, "pt_init: M must be a power of two in [2, 64]");
+  if (!host_temps) return fail(c, NFM_EINVAL, "pt_init: null temperatures");
+  for (int s = 0; s < M; ++s)
+    if (!(host_temps[s] > 0.0 && std::isfinite(host_temps[s])) || (s > 0 && !(host_temps[s] > host_temps[s - 1])))
+      return fail(c, NFM_EINVAL, "pt_init: temperatures must be positive, finite and strictly increasing");
+  NFM_TRY(c, {
+    // Metropolis rows (u-order, pad 0): step m = 3 - u changes E by 4m, x = exp(-(1/T)(4m)).
+    std::vector<uint32_t> metro((size_t)M * 8, 0u);
+    for (int s = 0; s < M; ++s) {
+      const double beta = 1.0 / host_temps[s];
+      for (int u = 0; u <= 6; ++u) {
+        const int m = 3 - u;
+        metro[(size_t)s * 8 + u] = m <= 0 ? 0xFFFFFFFFu : pt_quantize(std::exp(-beta * (double)(4 * m)));
+      }
+    }
+    // Exchange rows: pair (s, s+1), d = (E_{s+1} - E_s)/4 >= 1, x = exp((1/T_{s+1} - 1/T_s)(4d));
+    // width D = first d at which every pair's threshold is 0 (larger d clamp to it exactly).
+    const int cap = c->lay.pt_dcap;
+    int D = cap;
+    for (int d = 1; d <= cap; ++d) {
+      bool zero = true;
+      for (int s = 0; s + 1 < M && zero; ++s) {
+        const double db = 1.0 / host_temps[s + 1] - 1.0 / host_temps[s];
+        if (pt_quantize(std::exp(db * (double)(4 * d))) != 0u) zero = false;
+      }
+      if (zero) {
+        D = d;
+        break;
+      }
+    }
+    std::vector<uint32_t> swap((size_t)(M - 1) * D);
+    for (int s = 0; s + 1 < M; ++s) {
+      const double db = 1.0 / host_temps[s + 1] - 1.0 / host_temps[s];
+      for (int d = 1; d <= D; ++d) swap[(size_t)s * D + (d - 1)] = pt_quantize(std::exp(db * (double)(4 * d)));
+    }
+    std::vector<int32_t> slot(c->lay.total_walkers);
+    for (int64_t w = 0; w < c->lay.total_walkers; ++w) slot[w] = (int32_t)(w % M);  // walker offsets are multiples of 64
+    NFM_HIP(c, hipMemcpyAsync(c->d_pt_metro(), metro.data(), 4 * metro.size(), hipMemcpyHostToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->d_pt_swap(), swap.data(), 4 * swap.size(), hipMemcpyHostToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->d_pt_slot(), slot.data(), 4 * slot.size(), hipMemcpyHostToDevice, c->stream));
+    NFM_HIP(c, hipMemsetAsync(c->d_pt_acc(), 0, 8 * (size_t)c->lay.total_walkers, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    c->pt_M = M;
+    c->pt_D = D;
+    return NFM_OK;
+  })
+}
+
+nfm_status nfm_pt_set_tables(nfm_ctx* c, const uint32_t* host_metro, const uint32_t* host_swap, int32_t D) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_set_tables: call nfm_pt_init first");
+  if (!host_metro || !host_swap || D < 1 || D > c->lay.pt_dcap)
+    return fail(c, NFM_EINVAL, "pt_set_tables: null pointer or D outside [1, 3N/2 + 1]");
+  NFM_HIP(c, hipMemcpyAsync(c->d_pt_metro(), host_metro, 4 * 8 * (size_t)c->pt_M, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(c->d_pt_swap(), host_swap, 4 * (size_t)(c->pt_M - 1) * D, hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  c->pt_D = D;
+  return NFM_OK;
+}
+
+nfm_status nfm_pt_get_tables(nfm_ctx* c, uint32_t* host_metro, uint32_t* host_swap, int32_t* M, int32_t* D) {
+  NFM_GUARD(c);
+  if (!M || !D) return fail(c, NFM_EINVAL, "pt_get_tables: null pointer");
+  *M = c->pt_M;
+  *D = c->pt_D;
+  if (c->pt_M == 0) return NFM_OK;
+  if (host_metro)
+    NFM_HIP(c, hipMemcpyAsync(host_metro, c->d_pt_metro(), 4 * 8 * (size_t)c->pt_M, hipMemcpyDeviceToHost, c->stream));
+  if (host_swap)
+    NFM_HIP(c, hipMemcpyAsync(host_swap, c->d_pt_swap(), 4 * (size_t)(c->pt_M - 1) * c->pt_D, hipMemcpyDeviceToHost,
+                              c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_pt_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_run_sweeps: call nfm_pt_init first");
+  if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
+    return fail(c, NFM_ERANGE, "pt_run_sweeps: the sweep counter must stay below 2^32");
+  uint64_t done = 0;
+  while (done < n_sweeps) {
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(c->sweeps_per_launch, n_sweeps - done);
+    for (size_t g = 0; g < c->group_L.size(); ++g) {
+      nfm::SweepArgs a{};
+      a.reals = c->d_reals();
+      a.wave_real = c->d_waves() + c->group_first_wave[g];
+      a.wave_wl = c->d_waves() + c->lay.total_waves + c->group_first_wave[g];
+      a.spins = c->d_spins();
+      a.jk = c->d_jk();
+      a.ws = c->walker_state();
+      a.trace = c->d_trace();
+      a.trace_cap = c->trace_cap;
+      a.trace_t0 = c->trace_t0;
+      a.t0 = c->sweeps + done;
+      a.n_sweeps = chunk;
+      a.walker_seed = c->walker_seed;
+      a.pt_metro = c->d_pt_metro();
+      a.pt_swap = c->d_pt_swap();
+      a.pt_slot = c->d_pt_slot();
+      a.pt_acc = c->d_pt_acc();
+      a.pt_M = c->pt_M;
+      a.pt_D = c->pt_D;
+      hipError_t e = nfm::launch_pt_sweeps(c->group_L[g], a, (int)c->group_n_waves[g], c->stream);
+      if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("pt_sweeps: ") + hipGetErrorString(e));
+    }
+    done += chunk;
+  }
+  c->sweeps += n_sweeps;
+  return NFM_OK;
+}
+
+nfm_status nfm_pt_read_slots(nfm_ctx* c, int32_t* host_slots) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_read_slots: call nfm_pt_init first");
+  if (!host_slots) return fail(c, NFM_EINVAL, "pt_read_slots: null pointer");
+  NFM_HIP(c, hipMemcpyAsync(host_slots, c->d_pt_slot(), 4 * (size_t)c->lay.total_walkers, hipMemcpyDeviceToHost,
+                            c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_pt_set_slots(nfm_ctx* c, const int32_t* host_slots) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_set_slots: call nfm_pt_init first");
+  if (!host_slots) return fail(c, NFM_EINVAL, "pt_set_slots: null pointer");
+  NFM_TRY(c, {
+    const int M = c->pt_M;
+    std::vector<char> seen(M);
+    for (int64_t s0 = 0; s0 < c->lay.total_walkers; s0 += M) {
+      std::fill(seen.begin(), seen.end(), 0);
+      for (int k = 0; k < M; ++k) {
+        const int32_t v = host_slots[s0 + k];
+        if (v < 0 || v >= M || seen[v]) return fail(c, NFM_EINVAL, "pt_set_slots: each set needs a permutation of 0..M-1");
+        seen[v] = 1;
+      }
+    }
+    NFM_HIP(c, hipMemcpyAsync(c->d_pt_slot(), host_slots, 4 * (size_t)c->lay.total_walkers, hipMemcpyHostToDevice,
+                              c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    return NFM_OK;
+  })
+}
+
+nfm_status nfm_pt_read_exchanges(nfm_ctx* c, uint64_t* host_acc) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_read_exchanges: call nfm_pt_init first");
+  if (!host_acc) return fail(c, NFM_EINVAL, "pt_read_exchanges: null pointer");
+  const size_t n = (size_t)(c->lay.total_walkers / c->pt_M) * (size_t)(c->pt_M - 1);
+  NFM_HIP(c, hipMemcpyAsync(host_acc, c->d_pt_acc(), 8 * n, hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Round-trip statistics (Sec. III).
+
+nfm_status nfm_rt_stats(nfm_ctx* c, int32_t r0, int32_t count, uint64_t min_trips, double* host_tau,
+                        nfm_rt_summary* host_summary) {
+  NFM_GUARD(c);
+  if (r0 < 0 || count < 1 || r0 + count > c->n_real || !host_summary)
+    return fail(c, NFM_EINVAL, "rt_stats: bad realization range or null pointer");
+  static_assert(sizeof(nfm_rt_summary) == sizeof(nfm::RtSummaryDev), "layout");
+  hipError_t e = nfm::launch_reduce_real(c->d_reals(), c->n_real, c->walker_state(), c->d_rstats(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("reduce_real: ") + hipGetErrorString(e));
+  double* d_tau = (double*)(c->ws + c->lay.rt_tau);
+  nfm::RtSummaryDev* d_sum = (nfm::RtSummaryDev*)(c->ws + c->lay.rt_sum);
+  e = nfm::launch_rt_stats(c->d_reals(), c->d_rstats(), r0, count, min_trips, d_tau, d_sum, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rt_stats: ") + hipGetErrorString(e));
+  if (host_tau) NFM_HIP(c, hipMemcpyAsync(host_tau, d_tau, 8 * (size_t)count, hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(host_summary, d_sum, sizeof(nfm_rt_summary), hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
   return NFM_OK;
 }
 

@@ -26,6 +26,14 @@ hipError_t launch_unpack_spins(const RealInfo* reals, int r, int wl0, int count,
 hipError_t launch_energy(const RealInfo* reals, int n_real, int max_walkers, const uint32_t* jabi,
                          const uint32_t* spins, WalkerState ws, hipStream_t s);
 hipError_t launch_reduce_real(const RealInfo* reals, int n_real, WalkerState ws, RealStatsDev* out, hipStream_t s);
+// per-realization round-trip times and their population mean over [r0, r0 + count)
+struct RtSummaryDev {        // same layout as nfm_rt_summary
+  double tau_pop;
+  uint64_t trips;
+  int32_t n_used, n_censored;
+};
+hipError_t launch_rt_stats(const RealInfo* reals, const RealStatsDev* stats, int r0, int count, uint64_t min_trips,
+                           double* tau, RtSummaryDev* out, hipStream_t s);
 
 // tables.hip
 hipError_t launch_build_tables(RealInfo* reals, int n_real, const double* lnw, const int32_t* k_lo,
@@ -43,6 +51,7 @@ hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, Rec
 
 // sweep.hip
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s);
+hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s);
 bool sweep_supported(int L);
 
 }  // namespace nfm

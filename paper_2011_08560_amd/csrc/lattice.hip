@@ -281,4 +281,55 @@ hipError_t launch_reduce_real(const RealInfo* reals, int n_real, WalkerState ws,
   return hipGetLastError();
 }
 
+// Round-trip times (Sec. III): tau_i = (sum of completed-trip time) / (number of trips) / N in
+// sweeps, censored (NaN) below min_trips trips; tau_pop = mean of the uncensored tau_i. One block;
+// the sum runs as a fixed-shape tree, so the result does not depend on scheduling.
+__global__ void k_rt_stats(const RealInfo* __restrict__ reals, const RealStatsDev* __restrict__ st, int r0, int count,
+                           uint64_t min_trips, double* __restrict__ tau, RtSummaryDev* __restrict__ out) {
+  __shared__ double s_sum[256];
+  __shared__ uint64_t s_trips[256];
+  __shared__ int s_used[256];
+  double sum = 0.0;
+  uint64_t trips = 0;
+  int used = 0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const int r = r0 + i;
+    const RealStatsDev d = st[r];
+    trips += d.rt_count;
+    double ti = __builtin_nan("");
+    if (d.rt_count >= min_trips && d.rt_count > 0) {
+      ti = (double)d.rt_time / (double)d.rt_count / (double)reals[r].N;
+      sum += ti;
+      used += 1;
+    }
+    tau[i] = ti;
+  }
+  s_sum[threadIdx.x] = sum;
+  s_trips[threadIdx.x] = trips;
+  s_used[threadIdx.x] = used;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + s];
+      s_trips[threadIdx.x] += s_trips[threadIdx.x + s];
+      s_used[threadIdx.x] += s_used[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    RtSummaryDev o;
+    o.tau_pop = s_used[0] > 0 ? s_sum[0] / (double)s_used[0] : __builtin_nan("");
+    o.trips = s_trips[0];
+    o.n_used = s_used[0];
+    o.n_censored = count - s_used[0];
+    *out = o;
+  }
+}
+
+hipError_t launch_rt_stats(const RealInfo* reals, const RealStatsDev* stats, int r0, int count, uint64_t min_trips,
+                           double* tau, RtSummaryDev* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rt_stats, dim3(1), dim3(256), 0, s, reals, stats, r0, count, min_trips, tau, out);
+  return hipGetLastError();
+}
+
 }  // namespace nfm

@@ -11,7 +11,8 @@ namespace nfm {
 
 constexpr int kMaxL = 12;
 constexpr int kWave = 64;
-constexpr uint32_t kTagAcc = 1, kTagSpin = 2, kTagJ = 3;
+constexpr uint32_t kTagAcc = 1, kTagSpin = 2, kTagJ = 3, kTagPT = 4, kTagSwap = 5;
+constexpr int kMaxReplicas = 64;  // temperature slots of one parallel-tempering set
 
 // Kernel spin layout. A walker's lattice is split by colour c = (x+y+z)&1 and
 // plane z; the L/2 sites of colour c in row y of plane z (x = 2j + phi,
@@ -69,6 +70,12 @@ struct SweepArgs {
   uint32_t n_sweeps;
   uint32_t pad2;
   uint64_t walker_seed;
+  // parallel tempering (unused by the multicanonical kernel)
+  const uint32_t* pt_metro;  // M x 8 Metropolis thresholds, u-order
+  const uint32_t* pt_swap;   // (M - 1) x D exchange thresholds
+  int32_t* pt_slot;          // temperature slot of every walker
+  uint64_t* pt_acc;          // accepted exchanges per (set, pair)
+  int32_t pt_M, pt_D;
 };
 
 // Weight-recursion state of one realization (device and host mirror, same layout as nfm_rec_info).

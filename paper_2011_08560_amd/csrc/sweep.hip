@@ -111,19 +111,55 @@ __device__ __forceinline__ void track_attempt(Track& tr, int B, uint64_t tau, in
   }
 }
 
-template <int L, bool SPEC>
-__global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
+// Round-trip bookkeeping on energies, applied once per sweep (parallel tempering: a
+// configuration's energy is examined after each Metropolis phase).
+struct TrackE {
+  int Emin, state, newmin;
+  uint32_t trips;
+  uint64_t t_first, t_last;
+};
+
+__device__ __forceinline__ void track_energy(TrackE& tr, int E, uint64_t tau, int e_bot, int e_top) {
+  if (E < tr.Emin) tr.Emin = E;
+  if (E < e_bot) tr.newmin = 1;
+  if (E >= e_top) {
+    if (tr.state == 2) {
+      tr.trips += 1;
+      tr.t_last = tau;
+    }
+    if (tr.state == 0) tr.t_first = tau;
+    tr.state = 1;
+  } else if (E <= e_bot && tr.state == 1) {
+    tr.state = 2;
+  }
+}
+
+__device__ __forceinline__ int lds_load_i32(uint32_t byte_addr) {
+  return *(const __attribute__((address_space(3))) int*)(uintptr_t)byte_addr;
+}
+__device__ __forceinline__ void lds_store_i32(uint32_t byte_addr, int v) {
+  *(__attribute__((address_space(3))) int*)(uintptr_t)byte_addr = v;
+}
+
+// PT = false: multicanonical sweeps; the table row follows the walker's level.
+// PT = true: parallel tempering (Sec. II, Eq. (8)); the walkers of a realization form sets of
+// M configurations, the row is the configuration's temperature slot, and after every sweep the
+// slots (s, s+1) with s = t (mod 2) try an exchange.
+template <int L, bool SPEC, bool PT>
+__global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
   using G = Geo<L>;
   using PW = typename G::PW;
   constexpr int NWP = G::NWP, Q = G::Q, N = G::N;
   constexpr int NB = (G::BITS + 7) / 8;  // bytes of a plane-colour string
   constexpr int kZUnroll = L <= 4 ? L : 1;
+  static_assert(!(PT && SPEC), "the tempering row does not depend on the decision");
   extern __shared__ uint32_t stab[];
 
   const int r = A.wave_real[blockIdx.x];
   const int wl = A.wave_wl[blockIdx.x] + (int)threadIdx.x;
   const RealInfo& RI = A.reals[r];
-  const int row0 = RI.row0, rows = RI.rows, e_base = RI.e_base, walkers = RI.walkers;
+  const int row0 = PT ? 0 : RI.row0, rows = PT ? A.pt_M : RI.rows;
+  const int e_base = RI.e_base, walkers = RI.walkers;
   const int e_bot = RI.e_bot, e_top = RI.e_top;
   const uint32_t real_id = RI.real_id;
   const int64_t gw = RI.walker_off + wl;
@@ -133,13 +169,16 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
   // The dynamic LDS block is the kernel's only LDS, so it starts at address 0.
   {
     (void)stab;
-    const uint32_t* gt = A.tables + RI.table_off;
+    const uint32_t* gt = PT ? A.pt_metro : A.tables + RI.table_off;
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
       const int jj = e & 7;
       const int u = jj < 4 ? 3 - jj : (jj == 4 ? 7 : 11 - jj);
       *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = gt[(e & ~7) + u];
     }
   }
+  // tempering scratch after the table: energies by slot, decisions, exchange counters
+  const uint32_t sE = (uint32_t)rows * 32u, sD = sE + 256u, sAcc = sD + 256u;
+  if constexpr (PT) lds_store_i32(sAcc + 4u * threadIdx.x, 0);
   __syncthreads();
 
   // walker state -> registers. One array per (colour, word) so that each stays small
@@ -159,26 +198,42 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
         for (int z = 0; z < L; ++z) lat(c, w)[z] = sp[(int64_t)((c * L + z) * NWP + w) * walkers];
   }
   const int E0 = A.ws.E[gw];
-  int B = ((E0 - e_base) / 4 - row0) * 32;
+  int E = E0;        // tempering: the energy, updated per attempt
+  int slot = 0;      // tempering: the temperature slot
+  int B;
   Track tr;
-  tr.Bmin = ((A.ws.E_min[gw] - e_base) / 4 - row0) * 32;
-  tr.state = A.ws.rt_state[gw];
-  tr.newmin = A.ws.new_min[gw];
-  tr.trips = 0;
-  tr.t_first = A.ws.t_first[gw];
-  tr.t_last = A.ws.t_last[gw];
+  TrackE te;
+  if constexpr (PT) {
+    slot = A.pt_slot[gw];
+    B = slot * 32;
+    te.Emin = A.ws.E_min[gw];
+    te.state = A.ws.rt_state[gw];
+    te.newmin = A.ws.new_min[gw];
+    te.trips = 0;
+    te.t_first = A.ws.t_first[gw];
+    te.t_last = A.ws.t_last[gw];
+  } else {
+    B = ((E0 - e_base) / 4 - row0) * 32;
+    tr.Bmin = ((A.ws.E_min[gw] - e_base) / 4 - row0) * 32;
+    tr.state = A.ws.rt_state[gw];
+    tr.newmin = A.ws.new_min[gw];
+    tr.trips = 0;
+    tr.t_first = A.ws.t_first[gw];
+    tr.t_last = A.ws.t_last[gw];
+  }
 
   const int Bmax = (rows - 1) * 32;
   const int Btop = (ceil_div4(e_top - e_base) - row0) * 32;    // E >= e_top  <=> B >= Btop
   const int Bbot = (floor_div4(e_bot - e_base) - row0) * 32;   // E <= e_bot  <=> B <= Bbot
   const int Bnm = (ceil_div4(e_bot - e_base) - 1 - row0) * 32; // E <  e_bot  <=> B <= Bnm
-  Window win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+  Window win;
+  if constexpr (!PT) win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
 
   const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
   // Round keys in VGPRs: uniform values, but keeping them out of the scalar file leaves room for
   // the per-plane coupling words and constants without spilling scalar registers.
   PhiloxKeysV kv = philox_round_keys_v(key0, key1);
-  const uint32_t ctr3 = ((uint32_t)wl << 8) | kTagAcc;
+  const uint32_t ctr3 = ((uint32_t)wl << 8) | (PT ? kTagPT : kTagAcc);
   const uint32_t* jreal = A.jk + RI.jk_off;
 
   for (uint32_t s = 0; s < A.n_sweeps; ++s) {
@@ -274,7 +329,8 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
             if (q >= Q) break;
             const int y = q / G::H, j = q % G::H;
             const int p = y * G::F + j, w = p >> 5, b = p & 31;
-            const int Bacc = B + __builtin_amdgcn_sbfe((int)hi_cur, 2, 3) * 32;   // B after acceptance
+            const int mstep = __builtin_amdgcn_sbfe((int)hi_cur, 2, 3);      // E changes by 4 mstep
+            const int Bacc = B + mstep * 32;                                   // B after acceptance
             uint32_t hi_next = 0, th_rej = 0, th_acc = 0;
             if (SPEC && q + 1 < Q) {
               // both candidate thresholds of the next site, before this decision resolves
@@ -284,7 +340,11 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
             }
             const bool acc = min(rnd.v[i], 0xFFFFFFFEu) < th_cur;
             if (acc) Cw[w] ^= 1u << b;
-            B = acc ? Bacc : B;
+            if constexpr (PT) {
+              E += acc ? 4 * mstep : 0;
+            } else {
+              B = acc ? Bacc : B;
+            }
             if (q + 1 < Q) {
               if (SPEC) {
                 th_cur = acc ? th_acc : th_rej;
@@ -296,33 +356,73 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
             }
             Bq[i] = B;
           }
-          // Did an attempt of this group leave the window? Then replay the group exactly.
-          const int last = (4 * g + 3 < Q) ? 3 : (Q - 1) - 4 * g;
-          int bmin = Bq[0], bmax = Bq[0];
+          if constexpr (!PT) {
+            // Did an attempt of this group leave the window? Then replay the group exactly.
+            const int last = (4 * g + 3 < Q) ? 3 : (Q - 1) - 4 * g;
+            int bmin = Bq[0], bmax = Bq[0];
 #pragma unroll
-          for (int k = 1; k < 4; ++k) {
-            if (k > last) break;
-            bmin = min(bmin, Bq[k]);
-            bmax = max(bmax, Bq[k]);
-          }
-          if (bmin < win.lo || bmax > win.hi) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 1; k < 4; ++k) {
               if (k > last) break;
-              track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g + k), e_base, row0, e_bot, e_top);
+              bmin = min(bmin, Bq[k]);
+              bmax = max(bmax, Bq[k]);
             }
-            win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+            if (bmin < win.lo || bmax > win.hi) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                if (k > last) break;
+                track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g + k), e_base, row0, e_bot, e_top);
+              }
+              win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+            }
           }
         }
 #pragma unroll
         for (int w = 0; w < NWP; ++w) lat(c, w)[z] = Cw[w];
       }
     }
-    // end of sweep: histogram and trace
-    const int k = (B >> 5) + row0;
-    if (k >= 0 && k < RI.K) atomicAdd(A.hist + RI.level_off + k, 1ULL);  // always true for exact energies
-    if (t - A.trace_t0 < (uint64_t)A.trace_cap)
-      A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
+    if constexpr (PT) {
+      // end of the Metropolis phase: bookkeeping with stamp (t + 1) N, trace
+      track_energy(te, E, (t + 1u) * (uint64_t)N, e_bot, e_top);
+      if (t - A.trace_t0 < (uint64_t)A.trace_cap) A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = E;
+      // exchange phase: slots (s, s+1), s = t (mod 2), of each set of M lanes
+      const int M = A.pt_M;
+      const uint32_t base = threadIdx.x & ~(uint32_t)(M - 1);
+      lds_store_i32(sE + 4u * (base + (uint32_t)slot), E);
+      __syncthreads();
+      const int par = (int)(t & 1u);
+      const bool lower = ((slot & 1) == par) && (slot + 1 < M);
+      const bool upper = (slot >= 1) && (((slot - 1) & 1) == par);
+      int dec = 0;
+      if (lower) {
+        const int Eh = lds_load_i32(sE + 4u * (base + (uint32_t)slot + 1u));
+        const int d = (Eh - E) / 4;   // energies of one realization share their residue mod 4
+        uint32_t th = 0xFFFFFFFFu;
+        if (d > 0) th = A.pt_swap[slot * A.pt_D + min(d, A.pt_D) - 1];
+        const uint32_t set = (uint32_t)wl / (uint32_t)M;
+        const u32x4 rr = philox4x32_10_vk((uint32_t)(slot >> 2), (uint32_t)t, real_id, (set << 8) | kTagSwap, kv);
+        const int k4 = slot & 3;
+        const uint32_t rw = k4 == 0 ? rr.v[0] : k4 == 1 ? rr.v[1] : k4 == 2 ? rr.v[2] : rr.v[3];
+        dec = min(rw, 0xFFFFFFFEu) < th ? 1 : 0;
+        lds_store_i32(sD + 4u * (base + (uint32_t)slot), dec);
+        if (dec) {
+          const uint32_t ca = sAcc + 4u * (base + (uint32_t)slot);
+          lds_store_i32(ca, lds_load_i32(ca) + 1);
+        }
+      }
+      __syncthreads();
+      int nslot = slot;
+      if (lower && dec) nslot = slot + 1;
+      if (upper && lds_load_i32(sD + 4u * (base + (uint32_t)slot - 1u))) nslot = slot - 1;
+      slot = nslot;
+      B = slot * 32;
+      __syncthreads();
+    } else {
+      // end of sweep: histogram and trace
+      const int k = (B >> 5) + row0;
+      if (k >= 0 && k < RI.K) atomicAdd(A.hist + RI.level_off + k, 1ULL);  // always true for exact energies
+      if (t - A.trace_t0 < (uint64_t)A.trace_cap)
+        A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
+    }
   }
 
   // registers -> walker state
@@ -335,49 +435,74 @@ __global__ void __launch_bounds__(64) k_muca_sweeps(SweepArgs A) {
 #pragma unroll
         for (int z = 0; z < L; ++z) sp[(int64_t)((c * L + z) * NWP + w) * walkers] = lat(c, w)[z];
   }
-  A.ws.E[gw] = e_base + 4 * ((B >> 5) + row0);
-  A.ws.E_min[gw] = e_base + 4 * ((tr.Bmin >> 5) + row0);
-  A.ws.rt_state[gw] = tr.state;
-  A.ws.new_min[gw] = tr.newmin;
-  A.ws.rt_count[gw] += tr.trips;
-  A.ws.t_first[gw] = tr.t_first;
-  A.ws.t_last[gw] = tr.t_last;
+  if constexpr (PT) {
+    A.ws.E[gw] = E;
+    A.ws.E_min[gw] = te.Emin;
+    A.ws.rt_state[gw] = te.state;
+    A.ws.new_min[gw] = te.newmin;
+    A.ws.rt_count[gw] += te.trips;
+    A.ws.t_first[gw] = te.t_first;
+    A.ws.t_last[gw] = te.t_last;
+    A.pt_slot[gw] = slot;
+    // exchange counters of the pairs (s, s+1) of this lane's set, s = lane index in the set
+    const int M = A.pt_M;
+    const int cidx = (int)(threadIdx.x & (uint32_t)(M - 1));
+    if (cidx < M - 1) A.pt_acc[(gw / M) * (M - 1) + cidx] += (uint64_t)lds_load_i32(sAcc + 4u * threadIdx.x);
+  } else {
+    A.ws.E[gw] = e_base + 4 * ((B >> 5) + row0);
+    A.ws.E_min[gw] = e_base + 4 * ((tr.Bmin >> 5) + row0);
+    A.ws.rt_state[gw] = tr.state;
+    A.ws.new_min[gw] = tr.newmin;
+    A.ws.rt_count[gw] += tr.trips;
+    A.ws.t_first[gw] = tr.t_first;
+    A.ws.t_last[gw] = tr.t_last;
+  }
 }
 
-template <int L, bool SPEC>
-static hipError_t launch_LS(const SweepArgs& a, int n_waves, int lds_rows, hipStream_t s) {
+template <int L, bool SPEC, bool PT>
+static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, hipStream_t s) {
   // The kernel addresses its dynamic LDS block from address 0, which is only valid
   // when the compiler placed nothing else in LDS.
   static int checked = 0;
   if (!checked) {
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_muca_sweeps<L, SPEC>));
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps<L, SPEC, PT>));
     if (e != hipSuccess) return e;
     if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     checked = 1;
   }
-  const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t);
-  hipLaunchKernelGGL((k_muca_sweeps<L, SPEC>), dim3(n_waves), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_sweeps<L, SPEC, PT>), dim3(n_waves), dim3(64), lds_bytes, s, a);
   return hipGetLastError();
 }
 
 template <int L>
-static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s) {
-  return spec ? launch_LS<L, true>(a, n_waves, lds_rows, s) : launch_LS<L, false>(a, n_waves, lds_rows, s);
+static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, bool spec, bool pt, hipStream_t s) {
+  if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256, s);
+  const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t);
+  return spec ? launch_LS<L, true, false>(a, n_waves, lds, s) : launch_LS<L, false, false>(a, n_waves, lds, s);
+}
+
+static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, bool pt, hipStream_t s) {
+  switch (L) {
+    case 2: return launch_L<2>(a, n_waves, lds_rows, spec, pt, s);
+    case 4: return launch_L<4>(a, n_waves, lds_rows, spec, pt, s);
+    case 6: return launch_L<6>(a, n_waves, lds_rows, spec, pt, s);
+    case 8: return launch_L<8>(a, n_waves, lds_rows, spec, pt, s);
+    case 10: return launch_L<10>(a, n_waves, lds_rows, spec, pt, s);
+    case 12: return launch_L<12>(a, n_waves, lds_rows, spec, pt, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
 
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s) {
-  switch (L) {
-    case 2: return launch_L<2>(a, n_waves, lds_rows, spec, s);
-    case 4: return launch_L<4>(a, n_waves, lds_rows, spec, s);
-    case 6: return launch_L<6>(a, n_waves, lds_rows, spec, s);
-    case 8: return launch_L<8>(a, n_waves, lds_rows, spec, s);
-    case 10: return launch_L<10>(a, n_waves, lds_rows, spec, s);
-    case 12: return launch_L<12>(a, n_waves, lds_rows, spec, s);
-    default: return hipErrorInvalidValue;
-  }
+  return launch_any(L, a, n_waves, lds_rows, spec, false, s);
+}
+
+hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s) {
+  if (a.pt_M < 2 || a.pt_M > kMaxReplicas || (a.pt_M & (a.pt_M - 1)) != 0 || a.pt_D < 1) return hipErrorInvalidValue;
+  return launch_any(L, a, n_waves, 1, false, true, s);
 }
 
 }  // namespace nfm

@@ -39,6 +39,8 @@ REAL_DTYPE = np.dtype([("rt_count", np.uint64), ("rt_time", np.uint64), ("E_min"
 REC_DTYPE = np.dtype([("k_lo", np.int32), ("k_top", np.int32), ("profile", np.int32), ("converged", np.int32),
                       ("iterations", np.int32), ("k_lo_changed", np.int32), ("pl_dE", np.float64),
                       ("pl_alpha", np.float64), ("flatness", np.float64)], align=True)
+RT_SUMMARY_DTYPE = np.dtype([("tau_pop", np.float64), ("trips", np.uint64), ("n_used", np.int32),
+                             ("n_censored", np.int32)], align=True)
 PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
 
 _lib = None
@@ -95,6 +97,14 @@ def lib():
         "nfm_rec_set_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
         "nfm_set_tuning": (i32, [vp, vp]),
         "nfm_get_tuning": (i32, [vp, vp]),
+        "nfm_pt_init": (i32, [vp, i32, vp]),
+        "nfm_pt_set_tables": (i32, [vp, vp, vp, i32]),
+        "nfm_pt_get_tables": (i32, [vp, vp, vp, C.POINTER(i32), C.POINTER(i32)]),
+        "nfm_pt_run_sweeps": (i32, [vp, u64]),
+        "nfm_pt_read_slots": (i32, [vp, vp]),
+        "nfm_pt_set_slots": (i32, [vp, vp]),
+        "nfm_pt_read_exchanges": (i32, [vp, vp]),
+        "nfm_rt_stats": (i32, [vp, i32, i32, u64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -380,3 +390,52 @@ class Batch:
         t = np.zeros(2, np.int32)
         self._check(self._lib.nfm_get_tuning(self.ctx, t.ctypes.data), "get_tuning")
         return int(t[0]), int(t[1])
+
+    # parallel tempering
+    def pt_init(self, temps):
+        T = np.ascontiguousarray(temps, np.float64)
+        self._check(self._lib.nfm_pt_init(self.ctx, len(T), T.ctypes.data), "pt_init")
+
+    def pt_tables(self):
+        """(metro [M, 8], swap [M-1, D]) as on the device."""
+        M, D = C.c_int32(), C.c_int32()
+        self._check(self._lib.nfm_pt_get_tables(self.ctx, None, None, C.byref(M), C.byref(D)), "pt_get_tables")
+        metro = np.zeros((M.value, 8), np.uint32)
+        swap = np.zeros((max(M.value - 1, 0), D.value), np.uint32)
+        self._check(self._lib.nfm_pt_get_tables(self.ctx, metro.ctypes.data, swap.ctypes.data, C.byref(M),
+                                                C.byref(D)), "pt_get_tables")
+        return metro, swap
+
+    def pt_set_tables(self, metro, swap):
+        metro = np.ascontiguousarray(metro, np.uint32)
+        swap = np.ascontiguousarray(swap, np.uint32)
+        self._check(self._lib.nfm_pt_set_tables(self.ctx, metro.ctypes.data, swap.ctypes.data, swap.shape[1]),
+                    "pt_set_tables")
+
+    def pt_run_sweeps(self, n: int):
+        self._check(self._lib.nfm_pt_run_sweeps(self.ctx, n), "pt_run_sweeps")
+
+    def pt_slots(self) -> np.ndarray:
+        out = np.zeros(self.n_walkers, np.int32)
+        self._check(self._lib.nfm_pt_read_slots(self.ctx, out.ctypes.data), "pt_read_slots")
+        return out
+
+    def pt_set_slots(self, slots):
+        sl = np.ascontiguousarray(slots, np.int32)
+        self._check(self._lib.nfm_pt_set_slots(self.ctx, sl.ctypes.data), "pt_set_slots")
+
+    def pt_exchanges(self, M: int) -> np.ndarray:
+        """Accepted exchanges, [n_walkers / M, M - 1]."""
+        out = np.zeros((self.n_walkers // M, M - 1), np.uint64)
+        self._check(self._lib.nfm_pt_read_exchanges(self.ctx, out.ctypes.data), "pt_read_exchanges")
+        return out
+
+    # round-trip statistics
+    def rt_stats(self, r0: int = 0, count: Optional[int] = None, min_trips: int = 1):
+        """(tau per realization [count] in sweeps, NaN = censored; summary record)."""
+        count = self.n_real - r0 if count is None else count
+        tau = np.zeros(count, np.float64)
+        summ = np.zeros(1, RT_SUMMARY_DTYPE)
+        self._check(self._lib.nfm_rt_stats(self.ctx, r0, count, min_trips, tau.ctypes.data, summ.ctypes.data),
+                    "rt_stats")
+        return tau, summ[0]
