@@ -138,8 +138,8 @@ nfm_status nfm_get_couplings(nfm_ctx* ctx, int32_t r0, int32_t count, uint32_t* 
 /* Spins. nfm_init_spins draws every walker's start: bit i is bit i%32 of
  * output[m & 3] of counter (m >> 2, 0, id, (w << 8) | 2), m = i/32, key =
  * walker_seed; set bit <=> S = -1. Set/get copy walkers [w0, w0+count) (global
- * walker index; realization r owns [nfm_walker_offset(r), +walkers[r])), N int8 each.
- * Spins of walkers of different L cannot be mixed in one call. */
+ * walker index; realization r owns [nfm_walker_offset(r), +walkers[r])), N int8 each, back
+ * to back (a range may span realizations of different L: each walker takes its own N). */
 nfm_status nfm_init_spins(nfm_ctx* ctx);
 nfm_status nfm_set_spins(nfm_ctx* ctx, int64_t w0, int64_t count, const int8_t* host_spins);
 nfm_status nfm_get_spins(nfm_ctx* ctx, int64_t w0, int64_t count, int8_t* host_spins);
@@ -243,14 +243,38 @@ nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const dou
  *   speculate: -1 automatic, 0 off, 1 on. With speculation each attempt also loads the next
  *     site's two candidate thresholds (accepted / rejected) before its own decision resolves,
  *     which shortens a walker's serial chain at the cost of a second table read; automatic
- *     turns it on when a launch has fewer than 8 waves per compute unit.
- *   sweeps_per_launch: sweeps per kernel launch (0 = 1024). */
+ *     turns it on when a launch has fewer than 8 waves per compute unit (the persistent
+ *     schedule takes -1 as off).
+ *   sweeps_per_launch: sweeps per kernel launch (0 = 1024).
+ *   schedule: 0 = one launch per lattice size of the batch; 1 = one persistent launch for the
+ *     whole batch, whose workgroups take waves of walkers from a queue ordered by decreasing N
+ *     (longest first), so that realizations of uneven size share the GPU.
+ *   waves_per_cu: persistent schedule only, resident workgroups per compute unit (0 = as many
+ *     as fit). */
 typedef struct {
   int32_t speculate;
   int32_t sweeps_per_launch;
+  int32_t schedule;
+  int32_t waves_per_cu;
 } nfm_tuning;
 nfm_status nfm_set_tuning(nfm_ctx* ctx, const nfm_tuning* tuning);
 nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
+
+/* Autotuner for mixed batches (no passage of the paper: a launch-configuration search). Times
+ * every candidate tuning (speculation off/on x sweeps per launch {64, 256, 1024} x {per-size
+ * launches, persistent queue with as many workgroups as fit, 4 or 8 per CU}) for calib_sweeps
+ * sweeps on the batch itself, then restores spins, walker state and histograms, so the
+ * calibration leaves no trace in the results (the sweep counter does not move). The fastest
+ * candidate (spin-flip attempts per second) is applied and returned in *best. Results are cached
+ * per (device, CU count, mix of L and walkers) for the process and, when cache_path is not
+ * NULL, in that text file (one line per key; a cached key is applied without measuring, and
+ * *n_results is then 0). results may be NULL when max_results is 0. Needs couplings and tables. */
+typedef struct {
+  nfm_tuning tuning;
+  double attempts_per_s;
+} nfm_tune_result;
+nfm_status nfm_autotune(nfm_ctx* ctx, int32_t calib_sweeps, const char* cache_path, nfm_tune_result* results,
+                        int32_t max_results, int32_t* n_results, nfm_tuning* best);
 
 nfm_status nfm_sync(nfm_ctx* ctx);
 

@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,6 +30,7 @@ struct Layout {
   size_t reals, waves, jabi, jk, spins, ws_i32, ws_u64, tables, hist, lnw, klo, ktop, trace, rstats, staging, total;
   size_t recs, rec_f64, rec_vis;
   size_t pt_slot, pt_acc, pt_metro, pt_swap, rt_tau, rt_sum;
+  size_t order, counter, snap_spins, snap_i32, snap_u64, snap_hist;
   int32_t pt_dcap;            // exchange-table width capacity: max over the batch of 3N/2 + 1
   int64_t total_walkers, total_waves, levels_total, jabi_words, jk_words, spin_words, table_words;
   size_t staging_bytes;
@@ -99,6 +103,12 @@ bool make_layout(const nfm_batch_desc* d, Layout* lay, std::string* why) {
   l.pt_swap = take(4 * (size_t)(nfm::kMaxReplicas - 1) * (size_t)l.pt_dcap);
   l.rt_tau = take(8 * (size_t)d->n_real);
   l.rt_sum = take(sizeof(nfm::RtSummaryDev));
+  l.order = take(4 * (size_t)l.total_waves);
+  l.counter = take(256);
+  l.snap_spins = take(4 * (size_t)l.spin_words);
+  l.snap_i32 = take(4 * 4 * (size_t)l.total_walkers);
+  l.snap_u64 = take(8 * 3 * (size_t)l.total_walkers);
+  l.snap_hist = take(8 * (size_t)l.levels_total);
   l.total = off;
   *lay = l;
   return true;
@@ -118,6 +128,8 @@ struct nfm_ctx {
   bool couplings = false;
   int speculate = -1;                      // -1 auto, 0 off, 1 on
   uint32_t sweeps_per_launch = kMaxSweepsPerLaunch;
+  int schedule = 0;                        // 0: one launch per lattice size, 1: persistent work queue
+  int waves_per_cu = 0;                    // persistent grid: workgroups per CU (0 = as many as fit)
   int n_cu = 256;
   std::vector<RealInfo> reals;
   // waves grouped by L
@@ -319,7 +331,14 @@ nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_works
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
       c->n_cu = ncu;
     nfm_status st = NFM_OK;
-    if (hipMemcpyAsync(c->d_waves(), wr.data(), 4 * wr.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+    // work-queue order: longest items (largest N) first, realization order within a size
+    std::vector<int32_t> order(l.total_waves);
+    for (int64_t i = 0; i < l.total_waves; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return c->reals[wr[a]].N > c->reals[wr[b]].N;
+    });
+    if (hipMemcpyAsync(c->ws + l.order, order.data(), 4 * order.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_waves(), wr.data(), 4 * wr.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->d_waves() + l.total_waves, wwl.data(), 4 * wwl.size(), hipMemcpyHostToDevice,
                        c->stream) != hipSuccess ||
         hipMemsetAsync(c->ws + l.ws_i32, 0, 4 * 4 * (size_t)l.total_walkers, c->stream) != hipSuccess ||
@@ -421,6 +440,7 @@ static nfm_status spins_io(nfm_ctx* c, int64_t w0, int64_t count, const int8_t* 
     return fail(c, NFM_EINVAL, "spins: bad walker range or null pointer");
   NFM_TRY(c, {
     int64_t w = w0, done = 0;
+    size_t host_off = 0;  // walkers of different realizations may have different N
     while (done < count) {
       const int r = real_of_walker(c, w);
       const RealInfo& ri = c->reals[r];
@@ -429,18 +449,19 @@ static nfm_status spins_io(nfm_ctx* c, int64_t w0, int64_t count, const int8_t* 
       const size_t bytes = (size_t)n * ri.N;
       int8_t* stage = (int8_t*)c->d_staging();
       if (src) {
-        NFM_HIP(c, hipMemcpyAsync(stage, src + done * ri.N, bytes, hipMemcpyHostToDevice, c->stream));
+        NFM_HIP(c, hipMemcpyAsync(stage, src + host_off, bytes, hipMemcpyHostToDevice, c->stream));
         hipError_t e = nfm::launch_pack_spins(c->d_reals(), r, (int)wl0, (int)n, stage, c->d_spins(), c->stream);
         if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("pack_spins: ") + hipGetErrorString(e));
         NFM_HIP(c, hipStreamSynchronize(c->stream));
       } else {
         hipError_t e = nfm::launch_unpack_spins(c->d_reals(), r, (int)wl0, (int)n, c->d_spins(), stage, c->stream);
         if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("unpack_spins: ") + hipGetErrorString(e));
-        NFM_HIP(c, hipMemcpyAsync(dst + done * ri.N, stage, bytes, hipMemcpyDeviceToHost, c->stream));
+        NFM_HIP(c, hipMemcpyAsync(dst + host_off, stage, bytes, hipMemcpyDeviceToHost, c->stream));
         NFM_HIP(c, hipStreamSynchronize(c->stream));
       }
       done += n;
       w += n;
+      host_off += bytes;
     }
     return NFM_OK;
   })
@@ -521,6 +542,62 @@ nfm_status nfm_set_rt_bounds(nfm_ctx* c, int32_t r, int32_t e_bot, int32_t e_top
   return push_reals(c);
 }
 
+static nfm::SweepArgs muca_args(nfm_ctx* c, uint64_t t0, uint32_t n, int trace_cap) {
+  nfm::SweepArgs a{};
+  a.reals = c->d_reals();
+  a.wave_real = c->d_waves();
+  a.wave_wl = c->d_waves() + c->lay.total_waves;
+  a.spins = c->d_spins();
+  a.jk = c->d_jk();
+  a.tables = c->d_tables();
+  a.ws = c->walker_state();
+  a.hist = c->d_hist();
+  a.trace = c->d_trace();
+  a.trace_cap = trace_cap;
+  a.trace_t0 = c->trace_t0;
+  a.t0 = t0;
+  a.n_sweeps = n;
+  a.walker_seed = c->walker_seed;
+  return a;
+}
+
+// Launch n multicanonical sweeps starting at sweep t0 under the given tuning (no checks).
+static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int speculate, uint32_t per_launch,
+                                int schedule, int waves_per_cu, int trace_cap) {
+  int lds_all = 1;
+  for (const auto& ri : c->reals) lds_all = std::max(lds_all, ri.rows);
+  uint64_t done = 0;
+  while (done < n_sweeps) {
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(per_launch, n_sweeps - done);
+    nfm::SweepArgs a = muca_args(c, t0 + done, chunk, trace_cap);
+    if (schedule == 1) {
+      const bool spec = speculate == 1;
+      int wpc = waves_per_cu;
+      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all));
+      const int64_t grid = std::min<int64_t>(c->lay.total_waves, (int64_t)wpc * c->n_cu);
+      hipError_t e = nfm::launch_muca_queue(a, (const int32_t*)(c->ws + c->lay.order), (int)c->lay.total_waves,
+                                            (uint32_t*)(c->ws + c->lay.counter), (int)grid, lds_all, spec, c->stream);
+      if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_queue: ") + hipGetErrorString(e));
+    } else {
+      for (size_t g = 0; g < c->group_L.size(); ++g) {
+        const int L = c->group_L[g];
+        int lds_rows = 1;
+        for (const auto& ri : c->reals)
+          if (ri.L == L) lds_rows = std::max(lds_rows, ri.rows);
+        a.wave_real = c->d_waves() + c->group_first_wave[g];
+        a.wave_wl = c->d_waves() + c->lay.total_waves + c->group_first_wave[g];
+        // Speculative lookups shorten each walker's serial chain; they pay off when there are
+        // too few waves per SIMD to hide the LDS latency with other waves.
+        const bool spec = speculate >= 0 ? speculate == 1 : c->group_n_waves[g] < 2 * 4 * (int64_t)c->n_cu;
+        hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, spec, c->stream);
+        if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
+      }
+    }
+    done += chunk;
+  }
+  return NFM_OK;
+}
+
 nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
   NFM_GUARD(c);
   if (!c->couplings) return fail(c, NFM_ESTATE, "run_sweeps: couplings not set");
@@ -528,37 +605,9 @@ nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
     if (c->reals[r].rows < 1) return fail(c, NFM_ESTATE, "run_sweeps: no threshold table, realization " + std::to_string(r));
   if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
     return fail(c, NFM_ERANGE, "run_sweeps: the sweep counter must stay below 2^32");
-  uint64_t done = 0;
-  while (done < n_sweeps) {
-    const uint32_t chunk = (uint32_t)std::min<uint64_t>(c->sweeps_per_launch, n_sweeps - done);
-    for (size_t g = 0; g < c->group_L.size(); ++g) {
-      const int L = c->group_L[g];
-      int lds_rows = 1;
-      for (const auto& ri : c->reals)
-        if (ri.L == L) lds_rows = std::max(lds_rows, ri.rows);
-      nfm::SweepArgs a{};
-      a.reals = c->d_reals();
-      a.wave_real = c->d_waves() + c->group_first_wave[g];
-      a.wave_wl = c->d_waves() + c->lay.total_waves + c->group_first_wave[g];
-      a.spins = c->d_spins();
-      a.jk = c->d_jk();
-      a.tables = c->d_tables();
-      a.ws = c->walker_state();
-      a.hist = c->d_hist();
-      a.trace = c->d_trace();
-      a.trace_cap = c->trace_cap;
-      a.trace_t0 = c->trace_t0;
-      a.t0 = c->sweeps + done;
-      a.n_sweeps = chunk;
-      a.walker_seed = c->walker_seed;
-      // Speculative lookups shorten each walker's serial chain; they pay off when there are
-      // too few waves per SIMD to hide the LDS latency with other waves.
-      const bool spec = c->speculate >= 0 ? c->speculate == 1 : c->group_n_waves[g] < 2 * 4 * (int64_t)c->n_cu;
-      hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, spec, c->stream);
-      if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
-    }
-    done += chunk;
-  }
+  nfm_status st = muca_launches(c, c->sweeps, n_sweeps, c->speculate, c->sweeps_per_launch, c->schedule,
+                                c->waves_per_cu, c->trace_cap);
+  if (st != NFM_OK) return st;
   c->sweeps += n_sweeps;
   return NFM_OK;
 }
@@ -753,10 +802,14 @@ nfm_status nfm_rec_set_state(nfm_ctx* c, int32_t r, const double* b, const doubl
 
 nfm_status nfm_set_tuning(nfm_ctx* c, const nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
-  if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0)
-    return fail(c, NFM_EINVAL, "set_tuning: speculate in {-1,0,1}, sweeps_per_launch >= 0");
+  if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0 || t->schedule < 0 || t->schedule > 1 ||
+      t->waves_per_cu < 0 || t->waves_per_cu > 64)
+    return fail(c, NFM_EINVAL,
+                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch >= 0, schedule in {0,1}, waves_per_cu in [0,64]");
   c->speculate = t->speculate;
   c->sweeps_per_launch = t->sweeps_per_launch == 0 ? kMaxSweepsPerLaunch : (uint32_t)t->sweeps_per_launch;
+  c->schedule = t->schedule;
+  c->waves_per_cu = t->waves_per_cu;
   return NFM_OK;
 }
 
@@ -764,9 +817,136 @@ nfm_status nfm_get_tuning(const nfm_ctx* c, nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
   t->speculate = c->speculate;
   t->sweeps_per_launch = (int32_t)c->sweeps_per_launch;
+  t->schedule = c->schedule;
+  t->waves_per_cu = c->waves_per_cu;
   return NFM_OK;
 }
 
+// Key of the autotuning cache: device, CU count, and the batch's mix of (L, walkers).
+static std::string tune_key(nfm_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
+  for (auto& ch : dev)
+    if (ch == ' ' || ch == '|') ch = '_';
+  std::map<int, int64_t> mix;
+  for (const auto& r : c->reals) mix[r.L] += r.walkers;
+  std::string k = dev + ":" + std::to_string(c->n_cu);
+  for (const auto& kv : mix) k += ":L" + std::to_string(kv.first) + "x" + std::to_string(kv.second);
+  return k;
+}
+
+static std::map<std::string, nfm_tuning>& tune_cache() {
+  static std::map<std::string, nfm_tuning> m;
+  return m;
+}
+
+nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path, nfm_tune_result* results,
+                        int32_t max_results, int32_t* n_results, nfm_tuning* best) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "autotune: couplings not set");
+  for (int r = 0; r < c->n_real; ++r)
+    if (c->reals[r].rows < 1) return fail(c, NFM_ESTATE, "autotune: no threshold table, realization " + std::to_string(r));
+  if (calib_sweeps < 1 || max_results < 0 || (max_results > 0 && !results))
+    return fail(c, NFM_EINVAL, "autotune: calib_sweeps >= 1 and a results array of max_results entries");
+  if (c->sweeps + (uint64_t)calib_sweeps > (uint64_t)UINT32_MAX)
+    return fail(c, NFM_ERANGE, "autotune: the sweep counter must stay below 2^32");
+  NFM_TRY(c, {
+    const std::string key = tune_key(c);
+    int found = 0;
+    nfm_tuning hit{};
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      hit = it->second;
+      found = 1;
+    } else if (cache_path) {
+      std::ifstream f(cache_path);
+      std::string line;
+      while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        nfm_tuning t{};
+        if ((is >> k >> t.speculate >> t.sweeps_per_launch >> t.schedule >> t.waves_per_cu) && k == key) {
+          hit = t;
+          found = 1;
+        }
+      }
+    }
+    if (n_results) *n_results = 0;
+    if (found) {
+      tune_cache()[key] = hit;
+      nfm_status st = nfm_set_tuning(c, &hit);
+      if (st == NFM_OK && best) *best = hit;
+      return st;
+    }
+    // Snapshot the state the sweeps change, time every candidate on the live batch, restore.
+    const Layout& l = c->lay;
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.snap_spins, c->ws + l.spins, 4 * (size_t)l.spin_words, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.snap_i32, c->ws + l.ws_i32, 16 * (size_t)l.total_walkers, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.snap_u64, c->ws + l.ws_u64, 24 * (size_t)l.total_walkers, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.snap_hist, c->ws + l.hist, 8 * (size_t)l.levels_total, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<nfm_tuning> cand;
+    const int chunks[] = {64, 256, 1024};
+    for (int spec = 0; spec <= 1; ++spec)
+      for (int ch : chunks) {
+        cand.push_back(nfm_tuning{spec, ch, 0, 0});
+        cand.push_back(nfm_tuning{spec, ch, 1, 0});
+        for (int wpc : {4, 8})
+          if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc});
+      }
+    hipEvent_t e0, e1;
+    NFM_HIP(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(c, NFM_EDEVICE, "autotune: hipEventCreate failed");
+    }
+    double attempts = 0.0;
+    for (const auto& r : c->reals) attempts += (double)r.walkers * r.N;
+    attempts *= (double)calib_sweeps;
+    nfm_tuning bt = cand[0];
+    double best_rate = -1.0;
+    int nres = 0;
+    nfm_status st = NFM_OK;
+    // one untimed warm-up pass so that first-launch costs do not favour later candidates
+    st = muca_launches(c, c->sweeps, (uint64_t)std::min(calib_sweeps, 64), 0, kMaxSweepsPerLaunch, 0, 0, 0);
+    for (size_t i = 0; i < cand.size() && st == NFM_OK; ++i) {
+      const nfm_tuning& t = cand[i];
+      if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, NFM_EDEVICE, "autotune: event"); break; }
+      st = muca_launches(c, c->sweeps, (uint64_t)calib_sweeps, t.speculate, (uint32_t)t.sweeps_per_launch, t.schedule,
+                         t.waves_per_cu, 0);
+      if (st != NFM_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(c, NFM_EDEVICE, "autotune: timing failed");
+        break;
+      }
+      const double rate = attempts / (ms * 1e-3);
+      if (nres < max_results) results[nres++] = nfm_tune_result{t, rate};
+      if (rate > best_rate) {
+        best_rate = rate;
+        bt = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.spins, c->ws + l.snap_spins, 4 * (size_t)l.spin_words, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.ws_i32, c->ws + l.snap_i32, 16 * (size_t)l.total_walkers, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.ws_u64, c->ws + l.snap_u64, 24 * (size_t)l.total_walkers, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->ws + l.hist, c->ws + l.snap_hist, 8 * (size_t)l.levels_total, hipMemcpyDeviceToDevice, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    if (st != NFM_OK) return st;
+    if (n_results) *n_results = nres;
+    tune_cache()[key] = bt;
+    if (cache_path) {
+      std::ofstream f(cache_path, std::ios::app);
+      if (f) f << key << " " << bt.speculate << " " << bt.sweeps_per_launch << " " << bt.schedule << " " << bt.waves_per_cu
+               << "\n";
+    }
+    if (best) *best = bt;
+    return nfm_set_tuning(c, &bt);
+  })
+}
 
 // ------------------------------------------------------------------------------------------
 // Parallel tempering (Sec. II, Eq. (8)).

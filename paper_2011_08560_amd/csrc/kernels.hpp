@@ -51,6 +51,10 @@ hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, Rec
 
 // sweep.hip
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s);
+// persistent launch over all waves of the batch; order = wave indices, longest first
+hipError_t launch_muca_queue(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
+                             int lds_rows, bool spec, hipStream_t s);
+int queue_blocks_per_cu(bool spec, int lds_rows);  // resident workgroups per CU (0 on error)
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s);
 bool sweep_supported(int L);
 

@@ -146,17 +146,15 @@ __device__ __forceinline__ void lds_store_i32(uint32_t byte_addr, int v) {
 // M configurations, the row is the configuration's temperature slot, and after every sweep the
 // slots (s, s+1) with s = t (mod 2) try an exchange.
 template <int L, bool SPEC, bool PT>
-__global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
+__device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   using G = Geo<L>;
   using PW = typename G::PW;
   constexpr int NWP = G::NWP, Q = G::Q, N = G::N;
   constexpr int NB = (G::BITS + 7) / 8;  // bytes of a plane-colour string
   constexpr int kZUnroll = L <= 4 ? L : 1;
   static_assert(!(PT && SPEC), "the tempering row does not depend on the decision");
-  extern __shared__ uint32_t stab[];
-
-  const int r = A.wave_real[blockIdx.x];
-  const int wl = A.wave_wl[blockIdx.x] + (int)threadIdx.x;
+  const int r = A.wave_real[wave];
+  const int wl = A.wave_wl[wave] + (int)threadIdx.x;
   const RealInfo& RI = A.reals[r];
   const int row0 = PT ? 0 : RI.row0, rows = PT ? A.pt_M : RI.rows;
   const int e_base = RI.e_base, walkers = RI.walkers;
@@ -168,7 +166,6 @@ __global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
   // the threshold of the step m = j (j < 4) or m = j - 8 (j > 4), i.e. of u = 3 - m.
   // The dynamic LDS block is the kernel's only LDS, so it starts at address 0.
   {
-    (void)stab;
     const uint32_t* gt = PT ? A.pt_metro : A.tables + RI.table_off;
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
       const int jj = e & 7;
@@ -460,6 +457,46 @@ __global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
 }
 
 template <int L, bool SPEC, bool PT>
+__global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
+  extern __shared__ uint32_t stab[];  // addressed from LDS address 0 by sweep_wave
+  (void)stab;
+  sweep_wave<L, SPEC, PT>(A, (int)blockIdx.x);
+}
+
+// Persistent multicanonical launch over a batch of mixed lattice sizes: each workgroup takes
+// work items (one wave of walkers for this launch's sweeps) from a global counter until the
+// queue is empty. The queue lists waves longest-first (by N), so the last items to start are
+// the cheapest ones. Results do not depend on which workgroup runs which item.
+template <bool SPEC>
+__global__ void __launch_bounds__(64) k_sweeps_queue(SweepArgs A, const int32_t* __restrict__ order, int n_items,
+                                                     uint32_t* __restrict__ counter) {
+  extern __shared__ uint32_t stab[];
+  (void)stab;
+  for (;;) {
+    __syncthreads();  // the previous item's table reads are done before the next table is loaded
+    int item = 0;
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    item = __shfl(item, 0, 64);
+    if (item >= n_items) break;
+    const int wave = order[item];
+    switch (A.reals[A.wave_real[wave]].L) {
+      case 2: sweep_wave<2, SPEC, false>(A, wave); break;
+      case 4: sweep_wave<4, SPEC, false>(A, wave); break;
+      case 6: sweep_wave<6, SPEC, false>(A, wave); break;
+      case 8: sweep_wave<8, SPEC, false>(A, wave); break;
+      case 10: sweep_wave<10, SPEC, false>(A, wave); break;
+      case 12: sweep_wave<12, SPEC, false>(A, wave); break;
+      default: break;
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <int L, bool SPEC, bool PT>
 static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, hipStream_t s) {
   // The kernel addresses its dynamic LDS block from address 0, which is only valid
   // when the compiler placed nothing else in LDS.
@@ -498,6 +535,39 @@ bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
 
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s) {
   return launch_any(L, a, n_waves, lds_rows, spec, false, s);
+}
+
+template <bool SPEC>
+static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
+                                 int lds_rows, hipStream_t s) {
+  static int checked = 0;
+  if (!checked) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps_queue<SPEC>));
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+    checked = 1;
+  }
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1, 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), (size_t)lds_rows * 32, s, a, order, n_items, counter);
+  return hipGetLastError();
+}
+
+int queue_blocks_per_cu(bool spec, int lds_rows) {
+  int n = 0;
+  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
+                       : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, (size_t)lds_rows * 32) != hipSuccess) return 0;
+  return n;
+}
+
+hipError_t launch_muca_queue(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
+                             int lds_rows, bool spec, hipStream_t s) {
+  if (grid < 1 || n_items < 0) return hipErrorInvalidValue;
+  return spec ? launch_queue_S<true>(a, order, n_items, counter, grid, lds_rows, s)
+              : launch_queue_S<false>(a, order, n_items, counter, grid, lds_rows, s);
 }
 
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s) {

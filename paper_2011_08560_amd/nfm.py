@@ -42,6 +42,8 @@ REC_DTYPE = np.dtype([("k_lo", np.int32), ("k_top", np.int32), ("profile", np.in
 RT_SUMMARY_DTYPE = np.dtype([("tau_pop", np.float64), ("trips", np.uint64), ("n_used", np.int32),
                              ("n_censored", np.int32)], align=True)
 PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
+TUNING_FIELDS = ("speculate", "sweeps_per_launch", "schedule", "waves_per_cu")
+TUNE_RESULT_DTYPE = np.dtype([("tuning", np.int32, (4,)), ("attempts_per_s", np.float64)], align=True)
 
 _lib = None
 
@@ -105,6 +107,7 @@ def lib():
         "nfm_pt_set_slots": (i32, [vp, vp]),
         "nfm_pt_read_exchanges": (i32, [vp, vp]),
         "nfm_rt_stats": (i32, [vp, i32, i32, u64, vp, vp]),
+        "nfm_autotune": (i32, [vp, i32, C.c_char_p, vp, i32, C.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -252,8 +255,18 @@ class Batch:
 
     def set_spins(self, w0: int, S: np.ndarray):
         S = np.ascontiguousarray(S, np.int8)
-        N = int(self.Ls[self._real_of(w0)]) ** 3
-        count = S.size // N if S.ndim == 1 else S.shape[0]
+        if S.ndim == 1:   # walkers back to back, each with the N of its realization
+            count, used, w = 0, 0, w0
+            while used < S.size:
+                used += int(self.Ls[self._real_of(w)]) ** 3
+                count += 1
+                w += 1
+            if used != S.size:
+                raise ValueError("set_spins: array length does not end on a walker boundary")
+        else:
+            count = S.shape[0]
+        if self._walker_sizes(w0, count) != S.size:
+            raise ValueError("set_spins: array size does not match the walkers' lattice sizes")
         self._check(self._lib.nfm_set_spins(self.ctx, w0, count, S.ctypes.data), "set_spins")
 
     def get_spins(self, w0: int, count: int) -> np.ndarray:
@@ -382,14 +395,27 @@ class Batch:
                                                 info.ctypes.data), "rec_set_state")
 
     # launch tuning
-    def set_tuning(self, speculate: int = -1, sweeps_per_launch: int = 0):
-        t = np.array([speculate, sweeps_per_launch], np.int32)
+    def set_tuning(self, speculate: int = -1, sweeps_per_launch: int = 0, schedule: int = 0, waves_per_cu: int = 0):
+        t = np.array([speculate, sweeps_per_launch, schedule, waves_per_cu], np.int32)
         self._check(self._lib.nfm_set_tuning(self.ctx, t.ctypes.data), "set_tuning")
 
-    def get_tuning(self):
-        t = np.zeros(2, np.int32)
+    def get_tuning(self) -> dict:
+        t = np.zeros(4, np.int32)
         self._check(self._lib.nfm_get_tuning(self.ctx, t.ctypes.data), "get_tuning")
-        return int(t[0]), int(t[1])
+        return dict(zip(TUNING_FIELDS, (int(x) for x in t)))
+
+    def autotune(self, calib_sweeps: int = 256, cache_path: Optional[str] = None, max_results: int = 64):
+        """Time the candidate launch configurations on this batch (state restored afterwards),
+        apply the fastest. Returns (best tuning dict, list of (tuning dict, attempts/s))."""
+        res = np.zeros(max_results, TUNE_RESULT_DTYPE)
+        n = C.c_int32()
+        best = np.zeros(4, np.int32)
+        path = cache_path.encode() if cache_path else None
+        self._check(self._lib.nfm_autotune(self.ctx, calib_sweeps, path, res.ctypes.data if max_results else None,
+                                           max_results, C.byref(n), best.ctypes.data), "autotune")
+        table = [(dict(zip(TUNING_FIELDS, (int(x) for x in r["tuning"]))), float(r["attempts_per_s"]))
+                 for r in res[:n.value]]
+        return dict(zip(TUNING_FIELDS, (int(x) for x in best))), table
 
     # parallel tempering
     def pt_init(self, temps):
