@@ -33,25 +33,36 @@ sys.path.insert(0, ROOT)
 ALG_OPS_PER_ATTEMPT = 18.0
 # MI355X integer VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per cycle).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-SWEEPS_PER_LAUNCH = 1024  # the library splits runs into launches of at most this many sweeps
 
 CONFIGS = {
-    # name: (L, realizations, walkers per realization, sweeps per step, description)
-    "c2": (6, 1024, 64, 100_000, "L=6, 1024 realizations, power-law target a=1 (dE=1), 1e5 sweeps per weight iteration"),
-    "c3": (8, 4096, 64, 10_000, "L=8, 4096 realizations, power-law target (dE=96, alpha=-3.6), 1e4 sweeps per step"),
-    "c1": (4, 32, 64, 10_000, "L=4, 32 realizations, flat target, 1e4 sweeps per weight iteration"),
+    # name: (mix [(L, realizations)], walkers per realization, sweeps per step, description)
+    "c2": ([(6, 1024)], 64, 100_000, "L=6, 1024 realizations, power-law target a=1 (dE=1), 1e5 sweeps per weight iteration"),
+    "c3": ([(8, 4096)], 64, 10_000, "L=8, 4096 realizations, power-law target (dE=96, alpha=-3.6), 1e4 sweeps per step"),
+    "c1": ([(4, 32)], 64, 10_000, "L=4, 32 realizations, flat target, 1e4 sweeps per weight iteration"),
+    "c4": ([(4, 4096), (6, 2048), (8, 1024), (10, 512), (12, 256)], 64, 4_096,
+           "mixed L=4/6/8/10/12 x 4096/2048/1024/512/256 realizations, power-law target, autotuned launch"),
+    "c3pt": ([(8, 4096)], 64, 10_000, "L=8, 4096 realizations, parallel tempering with 32 temperatures "
+                                      "geometric in [0.2, 2] (two sets of 32 per realization), exchanges every sweep"),
 }
-PROFILES = {"c2": (1, 1.0, -1.0), "c3": (1, 96.0, -3.6), "c1": (0, 1.0, 0.0)}
+PROFILES = {"c2": (1, 1.0, -1.0), "c3": (1, 96.0, -3.6), "c1": (0, 1.0, 0.0), "c4": (1, 1.0, -1.0),
+            "c3pt": None}
 DSEED = 20110856
 
 
-def setup(nfm, L, R, W, profile):
-    b = nfm.Batch([L] * R, [W] * R, disorder_seed=DSEED, walker_seed=DSEED + 1, first_real_id=0)
+def setup(nfm, mix, W, profile):
+    Ls = [L for L, R in mix for _ in range(R)]
+    b = nfm.Batch(Ls, [W] * len(Ls), disorder_seed=DSEED, walker_seed=DSEED + 1, first_real_id=0)
     b.init_couplings()
     b.init_spins()
     b.compute_energies()
-    b.rec_init(*profile)
-    return b
+    if profile is None:
+        M = 32
+        b.pt_init([0.2 * 10.0 ** (m / (M - 1)) for m in range(M)])
+        for r, L in enumerate(Ls):        # a configuration at T = 2 sits near E/N = -1.4; ground states near -1.7
+            b.set_rt_bounds(r, int(-1.66 * L ** 3), int(-1.40 * L ** 3))
+    else:
+        b.rec_init(*profile)
+    return b, Ls
 
 
 def _oracle_iteration(args):
@@ -103,19 +114,39 @@ def main():
     import torch
     from paper_2011_08560_amd import nfm
 
-    L, R, W, S, desc = CONFIGS[args.config]
+    mix, W, S, desc = CONFIGS[args.config]
     S = args.sweeps or S
     W = args.walkers or W
     profile = PROFILES[args.config]
-    b = setup(nfm, L, R, W, profile)
-    b.set_tuning(speculate=args.speculate)
+    pt = profile is None
+    b, Ls = setup(nfm, mix, W, profile)
+    L = max(Ls)
+    R = len(Ls)
+    tuned = None
+    if args.config == "c4":
+        b.run_sweeps(64)                  # one short round so that the tables have their working shape
+        b.rec_update(0.5)
+        tuned, _ = b.autotune(calib_sweeps=256)
+    elif args.speculate != -1:
+        b.set_tuning(speculate=args.speculate)
     stream = torch.cuda.current_stream()
-    attempts_per_step = R * W * S * L ** 3
-    launches_per_step = math.ceil(S / SWEEPS_PER_LAUNCH)
+    attempts_per_step = W * S * sum(l ** 3 for l in Ls)
+    tn = b.get_tuning()
+    groups = 1 if len(mix) == 1 or (not pt and tn["schedule"] == 1) else len(mix)
+    launches_per_step = math.ceil(S / tn["sweeps_per_launch"]) * groups
+
+    def step():
+        if pt:
+            b.pt_run_sweeps(S)
+        else:
+            b.run_sweeps(S)
+
+    def update():
+        return None if pt else b.rec_update(0.5)
 
     for _ in range(args.warmup):
-        b.run_sweeps(S)
-        b.rec_update(0.5)
+        step()
+        update()
     torch.cuda.synchronize()
     trips0 = int(b.read_realizations()["rt_count"].sum())
 
@@ -125,9 +156,9 @@ def main():
     info = None
     for k in range(args.steps):
         ev[k][0].record(stream)
-        b.run_sweeps(S)
+        step()
         ev[k][1].record(stream)
-        info = b.rec_update(0.5)
+        info = update()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     trips = int(b.read_realizations()["rt_count"].sum()) - trips0
@@ -136,6 +167,8 @@ def main():
     attempts_per_launch = attempts_per_step / launches_per_step
     achieved = ALG_OPS_PER_ATTEMPT * attempts_per_launch / avg_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    kernel = ("k_sweeps<%d,PT>" % L) if pt else ("k_sweeps_queue" if tuned and tuned["schedule"] == 1
+                                                  else "k_sweeps<%d>" % L)
 
     line = {
         "metric": "spin-flip attempts/s per GPU",
@@ -150,20 +183,26 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 3D +-J EA {desc}; one step = sweeps + device weight update",
-                   "L": L, "realizations": R, "walkers_per_realization": W, "sweeps_per_step": S,
-                   "profile": {"kind": ["flat", "power", "invk"][profile[0]], "dE": profile[1], "alpha": profile[2]}},
+        "config": {"workload": f"{args.config}: 3D +-J EA {desc}; one step = "
+                               + ("PT sweeps" if pt else "sweeps + device weight update"),
+                   "mix": [[l, r] for l, r in mix], "realizations": R, "walkers_per_realization": W,
+                   "sweeps_per_step": S,
+                   "profile": None if pt else {"kind": ["flat", "power", "invk"][profile[0]], "dE": profile[1],
+                                               "alpha": profile[2]}},
         "round_trips_per_s": trips / wall,
-        "weight_iterations": {"done": int(info["iterations"].max()),
-                              "converged_fraction": float(info["converged"].mean()),
-                              "median_flatness": float(np.median(info["flatness"]))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": f"k_muca_sweeps<{L}>", "avg_launch_ms": avg_launch_s * 1e3,
+                     "kernel": kernel, "avg_launch_ms": avg_launch_s * 1e3,
                      "alg_ops_per_attempt": ALG_OPS_PER_ATTEMPT, "speculate": args.speculate},
     }
+    if info is not None:
+        line["weight_iterations"] = {"done": int(info["iterations"].max()),
+                                     "converged_fraction": float(info["converged"].mean()),
+                                     "median_flatness": float(np.median(info["flatness"]))}
+    if tuned is not None:
+        line["tuning"] = tuned
     b.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not pt and len(mix) == 1:
         line["cpu_baseline"] = cpu_baseline(L, W, profile)
     print(json.dumps(line))
 
