@@ -240,11 +240,11 @@ nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const dou
 
 /* Launch tuning of nfm_run_sweeps (results do not depend on it: the random stream is indexed
  * by sweep, site and walker, and all accumulation is integer).
- *   speculate: -1 automatic, 0 off, 1 on. With speculation each attempt also loads the next
- *     site's two candidate thresholds (accepted / rejected) before its own decision resolves,
- *     which shortens a walker's serial chain at the cost of a second table read; automatic
- *     turns it on when a launch has fewer than 8 waves per compute unit (the persistent
- *     schedule takes -1 as off).
+ *   speculate: -1 automatic (= off), 0 off, 1 on. With speculation each attempt also loads the
+ *     next site's two candidate thresholds (accepted / rejected) before its own decision
+ *     resolves, which shortens a walker's serial chain at the cost of a second table read. The
+ *     plain form overlaps its single table read with generator work instead, which measures
+ *     faster on gfx950 at every occupancy tried.
  *   sweeps_per_launch: sweeps per kernel launch (0 = 1024).
  *   schedule: 0 = one launch per lattice size of the batch; 1 = one persistent launch for the
  *     whole batch, whose workgroups take waves of walkers from a queue ordered by decreasing N

@@ -586,9 +586,9 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
           if (ri.L == L) lds_rows = std::max(lds_rows, ri.rows);
         a.wave_real = c->d_waves() + c->group_first_wave[g];
         a.wave_wl = c->d_waves() + c->lay.total_waves + c->group_first_wave[g];
-        // Speculative lookups shorten each walker's serial chain; they pay off when there are
-        // too few waves per SIMD to hide the LDS latency with other waves.
-        const bool spec = speculate >= 0 ? speculate == 1 : c->group_n_waves[g] < 2 * 4 * (int64_t)c->n_cu;
+        // Speculation is off unless asked for: the table read of the plain form is already
+        // overlapped with generator work, which costs fewer instructions than a second read.
+        const bool spec = speculate == 1;
         hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, spec, c->stream);
         if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
       }

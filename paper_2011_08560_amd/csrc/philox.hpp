@@ -80,4 +80,26 @@ __device__ __forceinline__ u32x4 philox4x32_10_vk(uint32_t c0, uint32_t c1, uint
   return r;
 }
 
+// Stepwise form, for interleaving a generator call with other work: rounds [R0, R1) of a call
+// whose state is s (initially the counter).
+struct PhiloxRun {
+  uint32_t c0, c1, c2, c3;
+};
+
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds(PhiloxRun& s, const PhiloxKeysV& kv) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int round = R0; round < R1; ++round) {
+    const uint64_t p0 = (uint64_t)M0 * s.c0;
+    const uint64_t p1 = (uint64_t)M1 * s.c2;
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), s.c1, kv.k0[round], 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), s.c3, kv.k1[round], 0x96);
+    s.c1 = (uint32_t)p1;
+    s.c3 = (uint32_t)p0;
+    s.c0 = n0;
+    s.c2 = n2;
+  }
+}
+
 }  // namespace nfm

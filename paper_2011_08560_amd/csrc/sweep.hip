@@ -141,6 +141,74 @@ __device__ __forceinline__ void lds_store_i32(uint32_t byte_addr, int v) {
   *(__attribute__((address_space(3))) int*)(uintptr_t)byte_addr = v;
 }
 
+// Acceptance of one attempt and its effect on the state, as one instruction sequence: the
+// comparison sets VCC, which then selects the new state and is shifted into the flip word F
+// (F = 2F + accepted). The two instructions between the comparison and the first reader of
+// VCC are the distance the hardware needs between a VALU write of VCC and a VALU read of it.
+//   level form:  B (row offset of the level, 32 per level) += 32 m on acceptance
+//   energy form: E += 4 m on acceptance (tempering: the row is the temperature slot)
+// m = the sign-extended 3-bit field at bits 2..4 of hi.
+// hn: the next site's gathered field; addr receives the next site's table address.
+__device__ __forceinline__ void accept_level(uint32_t rc, uint32_t th, uint32_t hi, uint32_t hn, int vBmax, int& B,
+                                             int& R, uint32_t& F, uint32_t& addr) {
+  int m, Bacc, Bn, Rn;
+  uint32_t Fn, an;
+  asm volatile("v_cmp_lt_u32_e32 vcc, %[rc], %[th]\n\t"
+      "v_bfe_i32 %[m], %[hi], 2, 3\n\t"
+      "v_lshl_add_u32 %[Bacc], %[m], 5, %[B]\n\t"
+      "v_cndmask_b32_e32 %[Bn], %[B], %[Bacc], vcc\n\t"
+      "v_addc_co_u32_e32 %[Fn], vcc, %[F], %[F], vcc\n\t"
+      "v_med3_i32 %[Rn], %[Bn], 0, %[Bmax]\n\t"
+      "v_and_or_b32 %[an], %[hn], 28, %[Rn]"
+      : [Bn] "=&v"(Bn), [Rn] "=&v"(Rn), [Fn] "=&v"(Fn), [m] "=&v"(m), [Bacc] "=&v"(Bacc), [an] "=&v"(an)
+      : [rc] "v"(rc), [th] "v"(th), [hi] "v"(hi), [hn] "v"(hn), [B] "v"(B), [F] "v"(F), [Bmax] "v"(vBmax)
+      : "vcc");
+  B = Bn;
+  R = Rn;
+  F = Fn;
+  addr = an;
+}
+
+__device__ __forceinline__ void accept_energy(uint32_t rc, uint32_t th, uint32_t hi, int& E, uint32_t& F) {
+  int m, Eacc, En;
+  uint32_t Fn;
+  asm volatile("v_cmp_lt_u32_e32 vcc, %[rc], %[th]\n\t"
+      "v_bfe_i32 %[m], %[hi], 2, 3\n\t"
+      "v_lshl_add_u32 %[Eacc], %[m], 2, %[E]\n\t"
+      "v_cndmask_b32_e32 %[En], %[E], %[Eacc], vcc\n\t"
+      "v_addc_co_u32_e32 %[Fn], vcc, %[F], %[F], vcc"
+      : [En] "=&v"(En), [Fn] "=&v"(Fn), [m] "=&v"(m), [Eacc] "=&v"(Eacc)
+      : [rc] "v"(rc), [th] "v"(th), [hi] "v"(hi), [E] "v"(E), [F] "v"(F)
+      : "vcc");
+  E = En;
+  F = Fn;
+}
+
+// Speculative form: the level and the clamped row after acceptance are computed beforehand
+// (the next site's thresholds for both outcomes are loaded meanwhile).
+__device__ __forceinline__ void accept_level_spec(uint32_t rc, uint32_t th, int Bacc, int Racc, int& B, int& R,
+                                                  uint32_t& F) {
+  int Bn, Rn;
+  uint32_t Fn;
+  asm("v_cmp_lt_u32_e32 vcc, %[rc], %[th]\n\t"
+      "s_nop 1\n\t"
+      "v_cndmask_b32_e32 %[Bn], %[B], %[Bacc], vcc\n\t"
+      "v_cndmask_b32_e32 %[Rn], %[R], %[Racc], vcc\n\t"
+      "v_addc_co_u32_e32 %[Fn], vcc, %[F], %[F], vcc"
+      : [Bn] "=&v"(Bn), [Rn] "=&v"(Rn), [Fn] "=&v"(Fn)
+      : [rc] "v"(rc), [th] "v"(th), [Bacc] "v"(Bacc), [Racc] "v"(Racc), [B] "v"(B), [R] "v"(R), [F] "v"(F)
+      : "vcc");
+  B = Bn;
+  R = Rn;
+  F = Fn;
+}
+
+__device__ __forceinline__ int clamp_row(int B, int Bmax) {
+  int R;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(R) : "v"(B), "s"(Bmax));
+  return R;
+}
+
 // PT = false: multicanonical sweeps; the table row follows the walker's level.
 // PT = true: parallel tempering (Sec. II, Eq. (8)); the walkers of a realization form sets of
 // M configurations, the row is the configuration's temperature slot, and after every sweep the
@@ -149,9 +217,9 @@ template <int L, bool SPEC, bool PT>
 __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   using G = Geo<L>;
   using PW = typename G::PW;
-  constexpr int NWP = G::NWP, Q = G::Q, N = G::N;
+  constexpr int NWP = G::NWP, Q = G::Q, N = G::N, H = G::H, FB = G::F;
   constexpr int NB = (G::BITS + 7) / 8;  // bytes of a plane-colour string
-  constexpr int kZUnroll = L <= 4 ? L : 1;
+  constexpr int kZUnroll = L <= 6 ? L : 1;
   static_assert(!(PT && SPEC), "the tempering row does not depend on the decision");
   const int r = A.wave_real[wave];
   const int wl = A.wave_wl[wave] + (int)threadIdx.x;
@@ -162,9 +230,13 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   const uint32_t real_id = RI.real_id;
   const int64_t gw = RI.walker_off + wl;
 
-  // threshold table -> LDS, each row permuted from u-order to m-order: LDS entry j holds
-  // the threshold of the step m = j (j < 4) or m = j - 8 (j > 4), i.e. of u = 3 - m.
-  // The dynamic LDS block is the kernel's only LDS, so it starts at address 0.
+  // LDS (the kernel's only LDS, so it starts at address 0):
+  //   [0, rows*32)        threshold table, each row permuted from u-order to m-order: entry j
+  //                       holds the threshold of the step m = j (j < 4) or m = j - 8 (j > 4);
+  //   tempering only      energies by slot, exchange decisions, exchange counters (3 x 256 B);
+  //   then                the realization's couplings in the kernel layout.
+  const uint32_t sE = (uint32_t)rows * 32u, sD = sE + 256u, sAcc = sD + 256u;
+  const uint32_t jbase = PT ? sAcc + 256u : sE;
   {
     const uint32_t* gt = PT ? A.pt_metro : A.tables + RI.table_off;
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
@@ -172,9 +244,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       const int u = jj < 4 ? 3 - jj : (jj == 4 ? 7 : 11 - jj);
       *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = gt[(e & ~7) + u];
     }
+    const uint32_t* jg = A.jk + RI.jk_off;
+    for (int e = threadIdx.x; e < jk_words(L); e += 64) lds_store_i32(jbase + 4u * (uint32_t)e, (int)jg[e]);
   }
-  // tempering scratch after the table: energies by slot, decisions, exchange counters
-  const uint32_t sE = (uint32_t)rows * 32u, sD = sE + 256u, sAcc = sD + 256u;
   if constexpr (PT) lds_store_i32(sAcc + 4u * threadIdx.x, 0);
   __syncthreads();
 
@@ -225,13 +297,15 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   const int Bnm = (ceil_div4(e_bot - e_base) - 1 - row0) * 32; // E <  e_bot  <=> B <= Bnm
   Window win;
   if constexpr (!PT) win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+  int R = clamp_row(B, Bmax);   // the table row in use: B clamped to the stored rows
+  int vBmax;                    // Bmax in a vector register (an operand of the decision sequence)
+  asm volatile("v_mov_b32 %0, %1" : "=v"(vBmax) : "s"(Bmax));
 
   const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
   // Round keys in VGPRs: uniform values, but keeping them out of the scalar file leaves room for
   // the per-plane coupling words and constants without spilling scalar registers.
   PhiloxKeysV kv = philox_round_keys_v(key0, key1);
   const uint32_t ctr3 = ((uint32_t)wl << 8) | (PT ? kTagPT : kTagAcc);
-  const uint32_t* jreal = A.jk + RI.jk_off;
 
   for (uint32_t s = 0; s < A.n_sweeps; ++s) {
     const uint64_t t = A.t0 + s;
@@ -252,12 +326,22 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
           Pw[w] = lat(1 - c, w)[zp];
           Mw[w] = lat(1 - c, w)[zm];
         }
-        const uint32_t* jz = jreal + (c * L + z) * 6 * NWP;
+        const uint32_t jz = jbase + 4u * (uint32_t)((c * L + z) * 6 * NWP);
         uint32_t Jw[6][NWP];
+        {
+          // 6 NWP words, 8-byte aligned: read as pairs, all issued before the first use
+          uint64_t jv[3 * NWP];
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
+          for (int k = 0; k < 3 * NWP; ++k)
+            jv[k] = *(const __attribute__((address_space(3))) uint64_t*)(uintptr_t)(jz + 8u * (uint32_t)k);
 #pragma unroll
-          for (int w = 0; w < NWP; ++w) Jw[k][w] = jz[k * NWP + w];
+          for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int w = 0; w < NWP; ++w) {
+              const int e = k * NWP + w;
+              Jw[k][w] = (uint32_t)(jv[e >> 1] >> (32 * (e & 1)));
+            }
+        }
 
         // flags: bit set <=> bond unsatisfied (S_i xor S_j xor [J = -1])
         const PW own = pack<L>(Cw), O = pack<L>(Ow), Zp = pack<L>(Pw), Zm = pack<L>(Mw);
@@ -303,55 +387,116 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
         const uint64_t tau_blk = tau0 + (uint64_t)(c * (N / 2) + z * Q);
         // m & 7 of site q in bits 2..4 (sign at bit 4) of a product high word
         auto gather = [&](int q) __attribute__((always_inline)) -> uint32_t {
-          const int y = q / G::H, j = q % G::H;
-          const int p = y * G::F + j, g8 = p >> 3, bb = p & 7;
+          const int y = q / H, j = q % H;
+          const int p = y * FB + j, g8 = p >> 3, bb = p & 7;
           // (2^26 + 2^19 + 2^12) >> bb: eight distinct constants in all
           return __umulhi(V[g8] & (0x01010100u << bb), 0x04081000u >> bb);
         };
-        auto lookup = [&](uint32_t hi, int Bv) __attribute__((always_inline)) -> uint32_t {
-          int R;
-          asm("v_med3_i32 %0, %1, 0, %2" : "=v"(R) : "v"(Bv), "s"(Bmax));
-          const uint32_t addr = (hi & 0x1cu) | (uint32_t)R;      // R is a multiple of 32
-          return *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr;
+        auto lookup = [&](uint32_t hi, int Rv) __attribute__((always_inline)) -> uint32_t {
+          // Rv is a multiple of 32 in [0, Bmax]; (hi & 0x1c) is 4 (m & 7)
+          return *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)((hi & 0x1cu) | (uint32_t)Rv);
         };
+        // Acceptance bits are shifted into F in site order, with a zero for every bit of a
+        // field beyond the row's H sites, and applied to the plane-colour string once per word.
+        uint32_t F = 0;
         int Bq[4];
         uint32_t hi_cur = gather(0);
-        uint32_t th_cur = lookup(hi_cur, B);
+        uint32_t th_cur = lookup(hi_cur, R);
+        uint32_t p_rej = th_cur, p_acc = th_cur;   // speculative pair of the current site
+        uint32_t addr_cur = (hi_cur & 0x1cu) | (uint32_t)R;
+        int Racc_prev = R;
+        // Random words of the next group are generated round by round between this group's
+        // attempts: each attempt issues its table read, then runs generator rounds and the next
+        // gather (independent of the read) before it waits for the threshold, so that the read's
+        // latency is covered by useful work even with a single wave per SIMD. Scheduling barriers
+        // keep that order.
+        constexpr int NG = (Q + 3) / 4;
+        PhiloxRun pr{ctr0, (uint32_t)t, real_id, ctr3};
+        philox_rounds<0, 10>(pr, kv);
+        uint32_t th_pt = 0;
+        if constexpr (PT) th_pt = th_cur;
 #pragma unroll
-        for (int g = 0; g < (Q + 3) / 4; ++g) {
-          const u32x4 rnd = philox4x32_10_vk(ctr0 | (uint32_t)g, (uint32_t)t, real_id, ctr3, kv);
+        for (int g = 0; g < NG; ++g) {
+          const u32x4 rnd = {{pr.c0, pr.c1, pr.c2, pr.c3}};
+          if (g + 1 < NG) pr = PhiloxRun{ctr0 | (uint32_t)(g + 1), (uint32_t)t, real_id, ctr3};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int q = 4 * g + i;
             if (q >= Q) break;
-            const int y = q / G::H, j = q % G::H;
-            const int p = y * G::F + j, w = p >> 5, b = p & 31;
-            const int mstep = __builtin_amdgcn_sbfe((int)hi_cur, 2, 3);      // E changes by 4 mstep
-            const int Bacc = B + mstep * 32;                                   // B after acceptance
-            uint32_t hi_next = 0, th_rej = 0, th_acc = 0;
-            if (SPEC && q + 1 < Q) {
-              // both candidate thresholds of the next site, before this decision resolves
-              hi_next = gather(q + 1);
-              th_rej = lookup(hi_next, B);
-              th_acc = lookup(hi_next, Bacc);
-            }
-            const bool acc = min(rnd.v[i], 0xFFFFFFFEu) < th_cur;
-            if (acc) Cw[w] ^= 1u << b;
-            if constexpr (PT) {
-              E += acc ? 4 * mstep : 0;
-            } else {
-              B = acc ? Bacc : B;
-            }
-            if (q + 1 < Q) {
-              if (SPEC) {
-                th_cur = acc ? th_acc : th_rej;
-                hi_cur = hi_next;
-              } else {
-                hi_cur = gather(q + 1);
-                th_cur = lookup(hi_cur, B);
+            const int y = q / H, j = q % H;
+            const int p = y * FB + j, w = p >> 5;
+            if constexpr (SPEC && !PT) {
+              const uint32_t rc = min(rnd.v[i], 0xFFFFFFFEu);
+              if (g + 1 < NG) {
+                if (i == 0) philox_rounds<0, 3>(pr, kv);
+                if (i == 1) philox_rounds<3, 5>(pr, kv);
+                if (i == 2) philox_rounds<5, 8>(pr, kv);
+                if (i == 3) philox_rounds<8, 10>(pr, kv);
               }
+              // thresholds of site q+1 for both outcomes of q are loaded before q is decided; the
+              // threshold of site q is picked from the pair loaded one site earlier
+              const int Bacc = B + __builtin_amdgcn_sbfe((int)hi_cur, 2, 3) * 32;
+              const int Racc = clamp_row(Bacc, Bmax);
+              uint32_t hi_next = 0, n_rej = 0, n_acc = 0;
+              if (q + 1 < Q) {
+                hi_next = gather(q + 1);
+                n_rej = lookup(hi_next, R);
+                n_acc = lookup(hi_next, Racc);
+              }
+              th_cur = (R == Racc_prev) ? p_acc : p_rej;
+              accept_level_spec(rc, th_cur, Bacc, Racc, B, R, F);
+              p_rej = n_rej;
+              p_acc = n_acc;
+              Racc_prev = Racc;
+              hi_cur = hi_next;
+            } else {
+              // (1) the threshold read: multicanonical, at the address the previous decision
+              //     computed; tempering, the next site's (the row is fixed), so that it is in
+              //     flight one attempt ahead
+              uint32_t th;
+              uint32_t hi_next = 0;
+              if constexpr (PT) {
+                th = th_pt;
+                if (q + 1 < Q) {
+                  hi_next = gather(q + 1);
+                  th_pt = lookup(hi_next, R);
+                }
+              } else {
+                th = *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr_cur;
+              }
+              // (2) independent work: generator rounds of the next group, next gather, clamp. Empty
+              //     volatile statements pin the order: they are ordered with the read and the
+              //     decision, and the rounds' inputs and outputs pass through them.
+              asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
+              if (g + 1 < NG) {
+                if (i == 0) philox_rounds<0, 3>(pr, kv);
+                if (i == 1) philox_rounds<3, 5>(pr, kv);
+                if (i == 2) philox_rounds<5, 8>(pr, kv);
+                if (i == 3) philox_rounds<8, 10>(pr, kv);
+              }
+              if constexpr (!PT) {
+                if (q + 1 < Q) hi_next = gather(q + 1);
+              }
+              const uint32_t rc = min(rnd.v[i], 0xFFFFFFFEu);
+              asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
+              // (3) the decision (and the next site's table address)
+              if constexpr (PT) {
+                accept_energy(rc, th, hi_cur, E, F);
+              } else {
+                accept_level(rc, th, hi_cur, hi_next, vBmax, B, R, F, addr_cur);
+              }
+              hi_cur = hi_next;
             }
             Bq[i] = B;
+            // end of a row inside the word: zeros for the field's unused bits; end of the word
+            // (or of the string): apply the flips
+            const bool last_in_word = (q + 1 == Q) || (((((q + 1) / H) * FB + (q + 1) % H) >> 5) != w);
+            if (last_in_word) {
+              Cw[w] ^= __builtin_bitreverse32(F) >> (31 - (p & 31));
+              F = 0;
+            } else if (j == H - 1 && FB > H) {
+              F <<= (FB - H);
+            }
           }
           if constexpr (!PT) {
             // Did an attempt of this group leave the window? Then replay the group exactly.
@@ -412,6 +557,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       if (upper && lds_load_i32(sD + 4u * (base + (uint32_t)slot - 1u))) nslot = slot - 1;
       slot = nslot;
       B = slot * 32;
+      R = B;
       __syncthreads();
     } else {
       // end of sweep: histogram and trace
@@ -514,8 +660,9 @@ static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, h
 
 template <int L>
 static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, bool spec, bool pt, hipStream_t s) {
-  if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256, s);
-  const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t);
+  const size_t jb = (size_t)jk_words(L) * 4;
+  if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
+  const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t) + jb;
   return spec ? launch_LS<L, true, false>(a, n_waves, lds, s) : launch_LS<L, false, false>(a, n_waves, lds, s);
 }
 
@@ -551,7 +698,8 @@ static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), (size_t)lds_rows * 32, s, a, order, n_items, counter);
+  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4, s,
+                     a, order, n_items, counter);
   return hipGetLastError();
 }
 
@@ -559,7 +707,9 @@ int queue_blocks_per_cu(bool spec, int lds_rows) {
   int n = 0;
   const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
                        : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, (size_t)lds_rows * 32) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4) !=
+      hipSuccess)
+    return 0;
   return n;
 }
 
