@@ -341,6 +341,15 @@ double orc_power_profile(double E, double E_g, double dE, double alpha) {
 void orc_rec_weights(int32_t K, int32_t e_base, int32_t k_lo, int32_t k_top, int32_t profile,
                      double pl_dE, double pl_alpha, const double* b,
                      double* S, double* lnP, double* lnW) {
+  orc_rec_weights_ext(K, e_base, k_lo, k_top, k_lo, profile, pl_dE, pl_alpha, b, S, lnP, lnW);
+}
+
+/* The same with a lower end k_low <= k_lo: a seeded estimate (prior DOS steps on levels
+ * not yet sampled) continues S below k_lo with its own steps, S(k) = S(k+1) - b(k), under
+ * the frozen profile lnP(k) = lnP(k_lo); arrays are then valid on [k_low, k_top].        */
+void orc_rec_weights_ext(int32_t K, int32_t e_base, int32_t k_lo, int32_t k_top, int32_t k_low,
+                         int32_t profile, double pl_dE, double pl_alpha, const double* b,
+                         double* S, double* lnP, double* lnW) {
   (void)K;
   S[k_top] = 0.0;
   for (int32_t k = k_top - 1; k >= k_lo; --k) S[k] = S[k + 1] - b[k];
@@ -363,6 +372,11 @@ void orc_rec_weights(int32_t K, int32_t e_base, int32_t k_lo, int32_t k_top, int
     }
     lnW[k] = -S[k] + lnP[k];
   }
+  for (int32_t k = k_lo - 1; k >= k_low; --k) {
+    S[k] = S[k + 1] - b[k];
+    lnP[k] = lnP[k_lo];
+    lnW[k] = -S[k] + lnP[k];
+  }
 }
 
 /* Accumulated-statistics recursion (Berg's multicanonical recursion written for
@@ -382,15 +396,28 @@ void orc_rec_update(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_min_s
                     const double* lnW_used, const double* lnP_used, const uint64_t* H,
                     double* b, double* p, uint8_t* visited, int32_t* k_lo_new,
                     double* flatness) {
+  orc_rec_update_ext(K, k_lo_used, k_top, k_lo_used, 0, k_min_seen, lnW_used, lnP_used, H, b, p, visited,
+                     k_lo_new, flatness);
+}
+
+/* The same for an estimate that may be seeded: lnW_used is valid on [k_low_used, k_top]
+ * (k_low_used <= k_lo_used; below it the lowest step continues), and with seeded != 0
+ * new levels below k_lo_used keep their seeded steps b(k) (with p(k) = 0) instead of
+ * copying b(k_lo_used).                                                              */
+void orc_rec_update_ext(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_low_used, int32_t seeded,
+                        int32_t k_min_seen, const double* lnW_used, const double* lnP_used,
+                        const uint64_t* H, double* b, double* p, uint8_t* visited, int32_t* k_lo_new,
+                        double* flatness) {
   (void)K;
   int32_t k_lo = k_min_seen < k_lo_used ? k_min_seen : k_lo_used;
   for (int32_t k = k_lo; k < k_lo_used; ++k) {
-    b[k] = b[k_lo_used];
+    if (!seeded) b[k] = b[k_lo_used];
     p[k] = 0.0;
   }
-  double d_lo = (k_lo_used < k_top) ? lnW_used[k_lo_used + 1] - lnW_used[k_lo_used] : 0.0;
+  int32_t low = k_low_used < k_lo_used ? k_low_used : k_lo_used;
+  double d_lo = (low < k_top) ? lnW_used[low + 1] - lnW_used[low] : 0.0;
   /* weights and profile as they were while sampling, on [k_lo, k_top] */
-  #define LNW_AT(k) ((k) >= k_lo_used ? lnW_used[k] : lnW_used[k_lo_used] - (double)(k_lo_used - (k)) * d_lo)
+  #define LNW_AT(k) ((k) >= low ? lnW_used[k] : lnW_used[low] - (double)(low - (k)) * d_lo)
   #define LNP_AT(k) ((k) >= k_lo_used ? lnP_used[k] : lnP_used[k_lo_used])
   int32_t prev = -1;
   for (int32_t k = k_lo; k <= k_top; ++k) {
@@ -420,6 +447,117 @@ void orc_rec_update(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_min_s
   #undef LNP_AT
   *flatness = (n > 0 && sum > 0.0) ? mn / (sum / (double)n) : 0.0;
   *k_lo_new = k_lo;
+}
+
+/* Seed of the DOS steps from a curve y_j = [S(E) - S(E_top)]/N on the energy grid
+ * e_j = -2 + 2j/255 (j = 0..255): S(k) = N y(E_k/N), linear between grid points and y_255
+ * above the grid; b(k) = S(k+1) - S(k) on [k_s, k_top), k_s the lowest level with
+ * E_k >= -2N. Returns k_s, or -1 (and leaves b alone) if any step is not positive and
+ * finite: the curve is then rejected and the plain start is kept.                  */
+static double seed_curve(const float* y, double e) {
+  double t = (e + 2.0) * 127.5;
+  if (t <= 0.0) return (double)y[0];
+  if (t >= 255.0) return (double)y[255];
+  int32_t j = (int32_t)floor(t);
+  double f = t - (double)j;
+  return (double)y[j] + f * ((double)y[j + 1] - (double)y[j]);
+}
+
+int32_t orc_seed_from_grid(int32_t N, int32_t e_base, int32_t k_top, const float* y, double* b) {
+  int32_t k_s = (-2 * N - e_base + 3) / 4;   /* ceil((-2N - e_base)/4), -2N - e_base >= 0 */
+  if (k_s < 0) k_s = 0;
+  if (k_s >= k_top) return -1;
+  for (int32_t k = k_s; k < k_top; ++k) {
+    double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
+    double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
+    double d = s1 - s0;
+    if (!(d > 0.0) || !isfinite(d)) return -1;
+  }
+  for (int32_t k = k_s; k < k_top; ++k) {
+    double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
+    double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
+    b[k] = s1 - s0;
+  }
+  return k_s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frustration statistics of one realization (inputs of the weight-seeding model).
+ * A plaquette (i; d1, d2) has the bonds J_d1(i), J_d2(i+e_d1), J_d1(i+e_d2), J_d2(i); it is
+ * frustrated when their product is -1. The elementary cube at corner i has six faces: the
+ * (x,y) plaquettes at i and i+e_z, (y,z) at i and i+e_x, (z,x) at i and i+e_y; an even
+ * number of them is frustrated. out[16]:
+ *   0..2  frustrated fraction of (x,y), (y,z), (z,x) plaquettes;  3  of all plaquettes;
+ *   4..6  negative-bond fraction along x, y, z;  7  of all bonds;  8  n_minus mod 2;
+ *   9..12 fraction of cubes with 0, 2, 4, 6 frustrated faces;
+ *   13..15 mean / 6, variance / 6 and fourth central moment / 96 of the site sums
+ *          sum_j J_ij over the six bonds of a site.                                 */
+static int32_t plaq_frustrated(int32_t L, const int8_t* J, int32_t i, int32_t d1, int32_t d2) {
+  int32_t N = L * L * L;
+  int32_t a = neighbour(L, i, d1, 1), c = neighbour(L, i, d2, 1);
+  int32_t prod = J[d1 * N + i] * J[d2 * N + a] * J[d1 * N + c] * J[d2 * N + i];
+  return prod < 0;
+}
+
+void orc_features(int32_t L, const int8_t* J, double* out) {
+  int32_t N = L * L * L;
+  int32_t orient[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+  int64_t fr[3] = {0, 0, 0}, neg[3] = {0, 0, 0}, cubes[4] = {0, 0, 0, 0};
+  for (int32_t o = 0; o < 3; ++o)
+    for (int32_t i = 0; i < N; ++i) fr[o] += plaq_frustrated(L, J, i, orient[o][0], orient[o][1]);
+  for (int32_t d = 0; d < 3; ++d)
+    for (int32_t i = 0; i < N; ++i) neg[d] += J[d * N + i] < 0;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t f = plaq_frustrated(L, J, i, 0, 1) + plaq_frustrated(L, J, neighbour(L, i, 2, 1), 0, 1) +
+                plaq_frustrated(L, J, i, 1, 2) + plaq_frustrated(L, J, neighbour(L, i, 0, 1), 1, 2) +
+                plaq_frustrated(L, J, i, 2, 0) + plaq_frustrated(L, J, neighbour(L, i, 1, 1), 2, 0);
+    cubes[f / 2] += 1;
+  }
+  double mean = 0.0;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t sum = 0;
+    for (int32_t d = 0; d < 3; ++d) sum += J[d * N + i] + J[d * N + neighbour(L, i, d, -1)];
+    mean += (double)sum;
+  }
+  mean /= (double)N;
+  double m2 = 0.0, m4 = 0.0;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t sum = 0;
+    for (int32_t d = 0; d < 3; ++d) sum += J[d * N + i] + J[d * N + neighbour(L, i, d, -1)];
+    double x = (double)sum - mean;
+    m2 += x * x;
+    m4 += x * x * x * x;
+  }
+  m2 /= (double)N;
+  m4 /= (double)N;
+  for (int32_t o = 0; o < 3; ++o) out[o] = (double)fr[o] / (double)N;
+  out[3] = (double)(fr[0] + fr[1] + fr[2]) / (double)(3 * N);
+  for (int32_t d = 0; d < 3; ++d) out[4 + d] = (double)neg[d] / (double)N;
+  out[7] = (double)(neg[0] + neg[1] + neg[2]) / (double)(3 * N);
+  out[8] = (double)((neg[0] + neg[1] + neg[2]) % 2);
+  for (int32_t c = 0; c < 4; ++c) out[9 + c] = (double)cubes[c] / (double)N;
+  out[13] = mean / 6.0;
+  out[14] = m2 / 6.0;
+  out[15] = m4 / 96.0;
+}
+
+/* Energy histogram of a canonical run as 64 bins of E/N over [-2, 0): bin
+ * floor((E/N + 2) 32), clipped into [0, 63]; fractions of all entries.            */
+void orc_hist_bins(int32_t K, int32_t e_base, int32_t N, const uint64_t* H, double* out) {
+  uint64_t tot = 0;
+  for (int32_t j = 0; j < 64; ++j) out[j] = 0.0;
+  for (int32_t k = 0; k < K; ++k) tot += H[k];
+  if (tot == 0) return;
+  uint64_t cnt[64] = {0};
+  for (int32_t k = 0; k < K; ++k) {
+    if (H[k] == 0) continue;
+    double e = (double)(e_base + 4 * k) / (double)N;
+    int32_t j = (int32_t)floor((e + 2.0) * 32.0);
+    if (j < 0) j = 0;
+    if (j > 63) j = 63;
+    cnt[j] += H[k];
+  }
+  for (int32_t j = 0; j < 64; ++j) out[j] = (double)cnt[j] / (double)tot;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -93,6 +93,19 @@ void orc_rec_update(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_min_s
                     double* b, double* p, uint8_t* visited, int32_t* k_lo_new,
                     double* flatness);
 
+void orc_rec_weights_ext(int32_t K, int32_t e_base, int32_t k_lo, int32_t k_top, int32_t k_low,
+                         int32_t profile, double pl_dE, double pl_alpha, const double* b,
+                         double* S, double* lnP, double* lnW);
+void orc_rec_update_ext(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_low_used, int32_t seeded,
+                        int32_t k_min_seen, const double* lnW_used, const double* lnP_used,
+                        const uint64_t* H, double* b, double* p, uint8_t* visited, int32_t* k_lo_new,
+                        double* flatness);
+int32_t orc_seed_from_grid(int32_t N, int32_t e_base, int32_t k_top, const float* y /* 256 */, double* b);
+
+/* Inputs of the weight-seeding model. */
+void orc_features(int32_t L, const int8_t* J, double* out /* 16 */);
+void orc_hist_bins(int32_t K, int32_t e_base, int32_t N, const uint64_t* H, double* out /* 64 */);
+
 /* Parallel tempering, Sec. II, Eq. (8). Temperatures strictly increasing. */
 void orc_pt_metro_table(int32_t M, const double* T, uint32_t* thr /* M x 8 */);
 int32_t orc_pt_swap_table(int32_t M, const double* T, int32_t d_cap, uint32_t* thr /* (M-1) x D or NULL */);

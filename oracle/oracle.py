@@ -92,6 +92,15 @@ def lib():
         L.orc_rec_update.argtypes = [i32, i32, i32, i32, P(np.float64), P(np.float64), P(np.uint64),
                                      P(np.float64), P(np.float64), P(np.uint8), C.POINTER(i32),
                                      C.POINTER(dbl)]
+        L.orc_rec_weights_ext.argtypes = [i32, i32, i32, i32, i32, i32, dbl, dbl, P(np.float64),
+                                          P(np.float64), P(np.float64), P(np.float64)]
+        L.orc_rec_update_ext.argtypes = [i32, i32, i32, i32, i32, i32, P(np.float64), P(np.float64), P(np.uint64),
+                                         P(np.float64), P(np.float64), P(np.uint8), C.POINTER(i32),
+                                         C.POINTER(dbl)]
+        L.orc_seed_from_grid.argtypes = [i32, i32, i32, P(np.float32), P(np.float64)]
+        L.orc_seed_from_grid.restype = i32
+        L.orc_features.argtypes = [i32, P(np.int8), P(np.float64)]
+        L.orc_hist_bins.argtypes = [i32, i32, i32, P(np.uint64), P(np.float64)]
         L.orc_pt_metro_table.argtypes = [i32, P(np.float64), P(np.uint32)]
         L.orc_pt_swap_table.argtypes = [i32, P(np.float64), i32, C.c_void_p]
         L.orc_pt_swap_table.restype = i32
@@ -228,6 +237,40 @@ def rec_update(K, k_lo_used, k_top, k_min_seen, lnW_used, lnP_used, H, b, p, vis
     return kl.value, fl.value
 
 
+def rec_weights_ext(K, eb, k_lo, k_top, k_low, profile, pl_dE, pl_alpha, b):
+    S = np.zeros(K, np.float64)
+    lnP = np.zeros(K, np.float64)
+    lnW = np.zeros(K, np.float64)
+    lib().orc_rec_weights_ext(K, eb, k_lo, k_top, k_low, profile, pl_dE, pl_alpha,
+                              np.ascontiguousarray(b, np.float64), S, lnP, lnW)
+    return S, lnP, lnW
+
+
+def rec_update_ext(K, k_lo_used, k_top, k_low_used, seeded, k_min_seen, lnW_used, lnP_used, H, b, p, visited):
+    kl = C.c_int32()
+    fl = C.c_double()
+    lib().orc_rec_update_ext(K, k_lo_used, k_top, k_low_used, 1 if seeded else 0, k_min_seen, lnW_used, lnP_used,
+                             np.ascontiguousarray(H, np.uint64), b, p, visited, C.byref(kl), C.byref(fl))
+    return kl.value, fl.value
+
+
+def seed_from_grid(N, eb, k_top, y, b):
+    """Fill b from a 256-point curve (in place); returns k_s or -1 (rejected)."""
+    return int(lib().orc_seed_from_grid(N, eb, k_top, np.ascontiguousarray(y, np.float32), b))
+
+
+def features(L, J) -> np.ndarray:
+    out = np.zeros(16, np.float64)
+    lib().orc_features(L, J, out)
+    return out
+
+
+def hist_bins(K, eb, N, H) -> np.ndarray:
+    out = np.zeros(64, np.float64)
+    lib().orc_hist_bins(K, eb, N, np.ascontiguousarray(H, np.uint64), out)
+    return out
+
+
 # --------------------------------------------------------------------------- weight iteration
 
 @dataclass
@@ -297,21 +340,25 @@ def recursion_init(rz: Realization) -> RecursionState:
 
 
 def weight_iterations(rz: Realization, st: RecursionState, n_iter: int, n_sweeps: int,
-                      profile=PROFILE_FLAT, pl_dE=1.0, pl_alpha=0.0, f_tol=0.5, stop=True):
+                      profile=PROFILE_FLAT, pl_dE=1.0, pl_alpha=0.0, f_tol=0.5, stop=True, k_seed=-1):
     """The weight iteration (Sec. II): build weights from the DOS estimate and the
     target profile, sample, update the estimate; stop at the first iteration whose
-    histogram is flat to f_tol with no new minimum. Returns a list of per-iteration
-    records (k_lo, flatness, converged)."""
+    histogram is flat to f_tol with no new minimum. With k_seed >= 0 the estimate's steps
+    b on [k_seed, k_lo) are a seeded prior (see seed_from_grid): they continue the weights
+    below k_lo and are kept when those levels are first reached. Returns a list of
+    per-iteration records (iteration, k_lo, flatness, converged)."""
     log = []
+    seeded = k_seed >= 0
     for it in range(n_iter):
-        S, lnP, lnW = rec_weights(rz.K, rz.eb, st.k_lo, st.k_top, profile, pl_dE, pl_alpha, st.b)
-        thr, row0 = build_thresholds(rz.K, lnW[st.k_lo:st.k_top + 1], st.k_lo, st.k_top)
+        k_low = min(k_seed, st.k_lo) if seeded else st.k_lo
+        S, lnP, lnW = rec_weights_ext(rz.K, rz.eb, st.k_lo, st.k_top, k_low, profile, pl_dE, pl_alpha, st.b)
+        thr, row0 = build_thresholds(rz.K, lnW[k_low:st.k_top + 1], k_low, st.k_top)
         e_lo = rz.eb + 4 * st.k_lo
         H, _ = sample(rz, thr, row0, e_lo, 0, n_sweeps)
         k_min = int(level_of(int(rz.w["E_min"].min()), rz.eb))
         k_lo_old = st.k_lo
-        st.k_lo, flat = rec_update(rz.K, st.k_lo, st.k_top, min(k_min, st.k_lo), lnW, lnP, H,
-                                   st.b, st.p, st.visited)
+        st.k_lo, flat = rec_update_ext(rz.K, st.k_lo, st.k_top, k_low, seeded, min(k_min, st.k_lo), lnW, lnP, H,
+                                       st.b, st.p, st.visited)
         conv = flat >= f_tol and st.k_lo == k_lo_old
         log.append((it, st.k_lo, flat, conv))
         if conv and stop:
