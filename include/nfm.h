@@ -224,6 +224,8 @@ typedef struct {
   int32_t k_lo_changed;  /* last update lowered k_lo */
   double pl_dE, pl_alpha;
   double flatness;       /* last update */
+  int32_t k_seed;        /* -1, or the lowest level of a seeded prior (nfm_rec_seed) */
+  int32_t pad;
 } nfm_rec_info;
 
 nfm_status nfm_rec_init(nfm_ctx* ctx, int32_t profile, double pl_dE, double pl_alpha);
@@ -326,6 +328,74 @@ typedef struct {
 } nfm_rt_summary;
 nfm_status nfm_rt_stats(nfm_ctx* ctx, int32_t r0, int32_t count, uint64_t min_trips, double* host_tau,
                         nfm_rt_summary* host_summary);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned start of the weight iteration (not in the paper: a model that guesses the density of
+ * states from the couplings, checked by the recursion of Sec. II, which remains the judge).
+ *
+ * nfm_set_canonical: canonical Metropolis tables at temperature T > 0 for every realization
+ *   (lnW = -E/T; the two top levels are given and the lowest step continues below, which is
+ *   the same constant step), for the short run whose histogram feeds the model.
+ * nfm_features: dev_x (device, n_real x 81 floats) receives per realization: L/12; the
+ *   frustrated fraction of (x,y), (y,z), (z,x) plaquettes and of all (a plaquette (i; d1, d2)
+ *   has bonds J_d1(i), J_d2(i+e_d1), J_d1(i+e_d2), J_d2(i), frustrated when their product is
+ *   -1); the negative-bond fraction along x, y, z and of all bonds; n_minus mod 2; the fraction
+ *   of elementary cubes with 0, 2, 4, 6 frustrated faces; mean/6, variance/6 and fourth central
+ *   moment/96 of the site sums sum_j J_ij; then 64 bins of E/N over [-2, 0) (bin
+ *   floor((E/N + 2) 32) clipped to [0, 63]) of the current level histogram, as fractions.
+ * nfm_rec_seed: a seeded prior on the DOS steps. For realization r with host_k_seed[r] >= 0
+ *   (and < k_top): b(k) = host_b[level offset + k] on [k_seed, k_top), accumulated weights p
+ *   cleared. A seeded estimate continues S below k_lo with its own steps (profile frozen at
+ *   k_lo), so weights and tables cover [min(k_seed, k_lo), k_top], and levels reached for the
+ *   first time keep their seeded steps (unseeded: they copy the lowest known step). k_lo still
+ *   comes from the walkers, and round trips, flatness and convergence are defined as before.
+ *   Weights, tables and bounds are rebuilt. Needs nfm_rec_init. host_k_seed = -1: unchanged.
+ * nfm_rec_seed_grid: the same from curves y (device, n_real x 256 floats) with y_j = [S(E) -
+ *   S(E_top)]/N on e_j = -2 + 2j/255: S(k) = N y(E_k/N), linear between grid points, y_255
+ *   above; b(k) = S(k+1) - S(k) on [k_s, k_top), k_s = lowest level with E >= -2N. A curve with
+ *   a step that is not positive and finite is rejected and the realization keeps its plain
+ *   start. host_k_seed (optional, n_real) receives k_s or -1. */
+nfm_status nfm_set_canonical(nfm_ctx* ctx, double T);
+nfm_status nfm_features(nfm_ctx* ctx, float* dev_x);
+nfm_status nfm_rec_seed(nfm_ctx* ctx, const double* host_b, const int32_t* host_k_seed);
+nfm_status nfm_rec_seed_grid(nfm_ctx* ctx, const float* dev_curves, int32_t* host_k_seed);
+
+/* The model: 81 inputs, normalized per input as (x - mean)/sd; three hidden layers of 128 with
+ * GELU (z Phi(z), erf form); 256 linear outputs (the curve y above). Parameter vector
+ * (nfm_mlp_n_params() floats, weights row-major [in][out]): W0 [96 x 128] (rows 81..95 padding,
+ * zero), b0 [128], W1 [128 x 128], b1, W2 [128 x 128], b2, W3 [128 x 256], b3 [256].
+ * Training in FP32: masked mean squared error L = sum m (y - t)^2 / sum m over a batch, its
+ * gradient by back-propagation, Adam with bias correction. Inference in BF16 (weights and
+ * activations rounded to nearest even, FP32 accumulation). Products run on the matrix cores.
+ * The context owns no memory: the caller's device workspace of nfm_mlp_workspace_bytes(). Device
+ * pointers: x [B x 81], t and mask [B x 256], y [B x 256] floats, B in [1, batch_max]. */
+typedef struct nfm_mlp nfm_mlp;
+int32_t nfm_mlp_n_params(void);
+nfm_status nfm_mlp_workspace_bytes(int32_t batch_max, size_t* bytes);
+nfm_status nfm_mlp_create(nfm_mlp** out, int32_t batch_max, void* dev_workspace, size_t workspace_bytes,
+                          int device, void* hip_stream);
+void nfm_mlp_destroy(nfm_mlp* mlp);
+const char* nfm_mlp_last_error(const nfm_mlp* mlp);
+/* Glorot-uniform weights from the Philox stream (counter (q >> 2, layer, 0, 6), key = seed),
+ * zero biases, identity normalization, optimizer state cleared. */
+nfm_status nfm_mlp_init(nfm_mlp* mlp, uint64_t seed);
+/* host_params (n_params floats) and/or host_norm (mean[81] then sd[81]); setting parameters
+ * clears the optimizer state. */
+nfm_status nfm_mlp_set_params(nfm_mlp* mlp, const float* host_params, const float* host_norm);
+nfm_status nfm_mlp_get_params(nfm_mlp* mlp, float* host_params, float* host_norm);
+nfm_status nfm_mlp_get_grads(nfm_mlp* mlp, float* host_grads);
+nfm_status nfm_mlp_forward(nfm_mlp* mlp, const float* dev_x, int32_t B, float* dev_y);
+/* Loss and gradient (kept for nfm_mlp_adam); host_loss (optional) synchronizes. */
+nfm_status nfm_mlp_loss_grad(nfm_mlp* mlp, const float* dev_x, const float* dev_t, const float* dev_mask,
+                             int32_t B, float* host_loss);
+nfm_status nfm_mlp_adam(nfm_mlp* mlp, float lr, float beta1, float beta2, float eps);
+/* loss_grad + adam(lr, 0.9, 0.999, 1e-8), asynchronous. */
+nfm_status nfm_mlp_train_step(nfm_mlp* mlp, const float* dev_x, const float* dev_t, const float* dev_mask,
+                              int32_t B, float lr);
+nfm_status nfm_mlp_last_loss(nfm_mlp* mlp, float* host_loss);
+/* BF16 copy of the current weights, then inference with it. */
+nfm_status nfm_mlp_to_bf16(nfm_mlp* mlp);
+nfm_status nfm_mlp_infer_bf16(nfm_mlp* mlp, const float* dev_x, int32_t B, float* dev_y);
 
 #ifdef __cplusplus
 }

@@ -783,7 +783,8 @@ nfm_status nfm_rec_set_state(nfm_ctx* c, int32_t r, const double* b, const doubl
   if (r < 0 || r >= c->n_real || !b || !p || !lnP || !lnW || !visited || !info)
     return fail(c, NFM_EINVAL, "rec_set_state: bad arguments");
   const RealInfo& ri = c->reals[r];
-  if (info->k_lo < 0 || info->k_top >= ri.K || info->k_lo > info->k_top || !valid_profile(info->profile, info->pl_dE, info->pl_alpha))
+  if (info->k_lo < 0 || info->k_top >= ri.K || info->k_lo > info->k_top || !valid_profile(info->profile, info->pl_dE, info->pl_alpha) ||
+      info->k_seed < -1 || info->k_seed >= info->k_top)
     return fail(c, NFM_EINVAL, "rec_set_state: bad level range or profile");
   const int64_t off = ri.level_off;
   const size_t n = (size_t)nfm::level_capacity(ri.N);
@@ -1130,6 +1131,67 @@ nfm_status nfm_rt_stats(nfm_ctx* c, int32_t r0, int32_t count, uint64_t min_trip
   if (host_tau) NFM_HIP(c, hipMemcpyAsync(host_tau, d_tau, 8 * (size_t)count, hipMemcpyDeviceToHost, c->stream));
   NFM_HIP(c, hipMemcpyAsync(host_summary, d_sum, sizeof(nfm_rt_summary), hipMemcpyDeviceToHost, c->stream));
   NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Learned seeding of the weight iteration.
+
+nfm_status nfm_rec_seed(nfm_ctx* c, const double* host_b, const int32_t* host_k_seed) {
+  NFM_GUARD(c);
+  if (!c->rec_ready) return fail(c, NFM_ESTATE, "rec_seed: call nfm_rec_init first");
+  if (!host_b || !host_k_seed) return fail(c, NFM_EINVAL, "rec_seed: null pointer");
+  NFM_TRY(c, {
+    std::vector<nfm_rec_info> info(c->n_real);
+    NFM_HIP(c, hipMemcpyAsync(info.data(), c->d_recs(), sizeof(nfm_rec_info) * c->n_real, hipMemcpyDeviceToHost,
+                              c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    for (int r = 0; r < c->n_real; ++r)
+      if (host_k_seed[r] < -1 || host_k_seed[r] >= info[r].k_top)
+        return fail(c, NFM_EINVAL, "rec_seed: k_seed must be -1 or in [0, k_top), realization " + std::to_string(r));
+    // staging: the caller-weights region (levels_total doubles) and the k_lo region (n_real ints)
+    NFM_HIP(c, hipMemcpyAsync(c->d_lnw(), host_b, 8 * (size_t)c->lay.levels_total, hipMemcpyHostToDevice, c->stream));
+    NFM_HIP(c, hipMemcpyAsync(c->d_klo(), host_k_seed, 4 * (size_t)c->n_real, hipMemcpyHostToDevice, c->stream));
+    hipError_t e = nfm::launch_rec_seed_copy(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->d_lnw(),
+                                             c->d_klo(), c->stream);
+    if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_seed: ") + hipGetErrorString(e));
+    e = nfm::launch_rec_weights(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->d_tables(), 1, c->stream);
+    if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_weights: ") + hipGetErrorString(e));
+    return pull_reals(c);
+  })
+}
+
+nfm_status nfm_rec_seed_grid(nfm_ctx* c, const float* dev_curves, int32_t* host_k_seed) {
+  NFM_GUARD(c);
+  if (!c->rec_ready) return fail(c, NFM_ESTATE, "rec_seed_grid: call nfm_rec_init first");
+  if (!dev_curves) return fail(c, NFM_EINVAL, "rec_seed_grid: null pointer");
+  hipError_t e = nfm::launch_rec_seed_grid(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), dev_curves,
+                                           c->d_klo(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_seed_grid: ") + hipGetErrorString(e));
+  e = nfm::launch_rec_weights(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->d_tables(), 1, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_weights: ") + hipGetErrorString(e));
+  if (host_k_seed)
+    NFM_HIP(c, hipMemcpyAsync(host_k_seed, c->d_klo(), 4 * (size_t)c->n_real, hipMemcpyDeviceToHost, c->stream));
+  return pull_reals(c);
+}
+
+nfm_status nfm_set_canonical(nfm_ctx* c, double T) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "set_canonical: couplings not set");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, NFM_EINVAL, "set_canonical: T must be positive and finite");
+  hipError_t e = nfm::launch_canonical_tables(c->d_reals(), c->n_real, T, c->d_lnw(), c->d_klo(), c->d_ktop(),
+                                              c->d_tables(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("canonical_tables: ") + hipGetErrorString(e));
+  return pull_reals(c);
+}
+
+nfm_status nfm_features(nfm_ctx* c, float* dev_x) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "features: couplings not set");
+  if (!dev_x) return fail(c, NFM_EINVAL, "features: null pointer");
+  hipError_t e = nfm::launch_features(c->d_reals(), c->n_real, c->d_jabi(), c->d_hist(), dev_x, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("features: ") + hipGetErrorString(e));
   return NFM_OK;
 }
 

@@ -46,8 +46,18 @@ hipError_t launch_rec_weights(RealInfo* reals, RecInfo* recs, int n_real, RecArr
                               int set_bounds, hipStream_t s);
 hipError_t launch_rec_update(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws,
                              unsigned long long* hist, uint32_t* tables, double f_tol, hipStream_t s);
+hipError_t launch_rec_seed_copy(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const double* src,
+                                const int32_t* k_seed, hipStream_t s);
+hipError_t launch_rec_seed_grid(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const float* curves,
+                                int32_t* k_seed_out, hipStream_t s);
 hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, uint32_t* tables,
                                  int profile, double pl_dE, double pl_alpha, hipStream_t s);
+
+// features.hip
+hipError_t launch_canonical_tables(RealInfo* reals, int n_real, double T, double* lnw, int32_t* k_lo, int32_t* k_top,
+                                   uint32_t* tables, hipStream_t s);
+hipError_t launch_features(const RealInfo* reals, int n_real, const uint32_t* jabi, const unsigned long long* hist,
+                           float* x, hipStream_t s);
 
 // sweep.hip
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s);

@@ -87,7 +87,14 @@ struct RecInfo {
   int32_t k_lo_changed;      // last update lowered k_lo
   double pl_dE, pl_alpha;    // power-law parameters of Eq. (5)
   double flatness;           // min/mean of H/P over visited levels, last update
+  int32_t k_seed;            // -1, or the lowest level of a seeded prior on the DOS steps
+  int32_t pad;
 };
+
+// lowest level of the weights and table: a seeded prior extends them below k_lo
+__host__ __device__ inline int rec_low(const RecInfo& ri) {
+  return (ri.k_seed >= 0 && ri.k_seed < ri.k_lo) ? ri.k_seed : ri.k_lo;
+}
 
 // Per-level FP64 arrays of the recursion (indexed by level offset + level).
 struct RecArrays {

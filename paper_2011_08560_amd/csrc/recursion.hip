@@ -20,7 +20,8 @@ __device__ __forceinline__ double rec_lnP_power(double E, double E_g, double dE,
   return alpha * log(E / (dE - E_g) + 1.0);
 }
 
-// S, ln P and lnW on [k_lo, k_top] from b (one thread).
+// S, ln P and lnW on [k_lo, k_top] from b (one thread); with a seeded prior also on
+// [k_seed, k_lo): S continues with the seeded steps under the frozen profile lnP(k_lo).
 __device__ void rec_weights_seq(const RecInfo& ri, int e_base, const double* b, double* S, double* lnP, double* lnW) {
   const int k_lo = ri.k_lo, k_top = ri.k_top;
   S[k_top] = 0.0;
@@ -46,6 +47,11 @@ __device__ void rec_weights_seq(const RecInfo& ri, int e_base, const double* b, 
     lnP[k] = lp;
     lnW[k] = -S[k] + lp;
   }
+  for (int k = k_lo - 1; k >= rec_low(ri); --k) {
+    S[k] = S[k + 1] - b[k];
+    lnP[k] = lnP[k_lo];
+    lnW[k] = -S[k] + lnP[k];
+  }
 }
 
 // One realization per block: weights from the current estimate, table, round-trip bounds.
@@ -62,7 +68,7 @@ __global__ void k_rec_weights(RealInfo* __restrict__ reals, RecInfo* __restrict_
     }
   }
   __syncthreads();
-  build_table_block(rp, A.lnW + off, rc->k_lo, rc->k_top, tables);
+  build_table_block(rp, A.lnW + off, rec_low(*rc), rc->k_top, tables);
 }
 
 // Initial state: b = p = 0, nothing visited, k_lo = lowest level of any walker's minimum.
@@ -100,6 +106,8 @@ __global__ void k_rec_init(RealInfo* __restrict__ reals, RecInfo* __restrict__ r
     rc->converged = 0;
     rc->iterations = 0;
     rc->k_lo_changed = 0;
+    rc->k_seed = -1;
+    rc->pad = 0;
   }
 }
 
@@ -124,16 +132,20 @@ __global__ void k_rec_update(RealInfo* __restrict__ reals, RecInfo* __restrict__
     const double* lnP = A.lnP + off;
     unsigned char* visited = A.visited + off;
     const int k_lo_used = rc->k_lo, k_top = rc->k_top;
+    const bool seeded = rc->k_seed >= 0;
     int k_min_seen = (s_min - rp->e_base) / 4;
     if (k_min_seen > k_lo_used) k_min_seen = k_lo_used;
     const int k_lo = k_min_seen;
+    // new levels: the lowest known step (plain) or their seeded steps, no accumulated weight
     for (int k = k_lo; k < k_lo_used; ++k) {
-      b[k] = b[k_lo_used];
+      if (!seeded) b[k] = b[k_lo_used];
       p[k] = 0.0;
     }
-    const double d_lo = (k_lo_used < k_top) ? lnW[k_lo_used + 1] - lnW[k_lo_used] : 0.0;
+    // weights used while sampling: stored on [low, k_top], continued with the lowest step below
+    const int low = rec_low(*rc);
+    const double d_lo = (low < k_top) ? lnW[low + 1] - lnW[low] : 0.0;
     auto lnw_at = [&](int k) {
-      return k >= k_lo_used ? lnW[k] : lnW[k_lo_used] - (double)(k_lo_used - k) * d_lo;
+      return k >= low ? lnW[k] : lnW[low] - (double)(low - k) * d_lo;
     };
     auto lnp_at = [&](int k) { return k >= k_lo_used ? lnP[k] : lnP[k_lo_used]; };
     int prev = -1;
@@ -172,7 +184,7 @@ __global__ void k_rec_update(RealInfo* __restrict__ reals, RecInfo* __restrict__
     rp->e_top = 0;
   }
   __syncthreads();
-  build_table_block(rp, A.lnW + off, rc->k_lo, rc->k_top, tables);
+  build_table_block(rp, A.lnW + off, rec_low(*rc), rc->k_top, tables);
   const int cap = level_capacity(rp->N);
   for (int k = threadIdx.x; k < cap; k += blockDim.x) hist[off + k] = 0ull;
 }
@@ -197,7 +209,85 @@ __global__ void k_rec_production(RealInfo* __restrict__ reals, RecInfo* __restri
     rp->e_top = 0;
   }
   __syncthreads();
-  build_table_block(rp, A.lnW + off, rc->k_lo, rc->k_top, tables);
+  build_table_block(rp, A.lnW + off, rec_low(*rc), rc->k_top, tables);
+}
+
+// Seeded prior from caller-given steps: b(k) = src(k) on [k_seed, k_top) for realizations with
+// k_seed >= 0, accumulated weights cleared; others untouched.
+__global__ void k_rec_seed_copy(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A,
+                                const double* __restrict__ src, const int32_t* __restrict__ k_seed) {
+  RealInfo* rp = reals + blockIdx.x;
+  RecInfo* rc = recs + blockIdx.x;
+  const int ks = k_seed[blockIdx.x];
+  if (ks < 0) return;
+  const int64_t off = rp->level_off;
+  const int cap = level_capacity(rp->N);
+  for (int k = threadIdx.x; k < cap; k += blockDim.x) {
+    if (k >= ks && k < rc->k_top) A.b[off + k] = src[off + k];
+    A.p[off + k] = 0.0;
+  }
+  if (threadIdx.x == 0) rc->k_seed = ks;
+}
+
+// Seeded prior from a curve y_j = [S(E) - S(E_top)]/N on the grid e_j = -2 + 2j/255 (256 floats
+// per realization): S(k) = N y(E_k/N), linear between grid points, y_255 above; b(k) = S(k+1) -
+// S(k) on [k_s, k_top), k_s = lowest level with E >= -2N. A curve with a step that is not
+// positive and finite is rejected (the realization keeps its plain start; k_seed_out = -1).
+__device__ __forceinline__ double seed_curve(const float* y, double e) {
+  const double t = (e + 2.0) * 127.5;
+  if (t <= 0.0) return (double)y[0];
+  if (t >= 255.0) return (double)y[255];
+  const int j = (int)floor(t);
+  const double f = t - (double)j;
+  return (double)y[j] + f * ((double)y[j + 1] - (double)y[j]);
+}
+
+__global__ void k_rec_seed_grid(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A,
+                                const float* __restrict__ curves, int32_t* __restrict__ k_seed_out) {
+  RealInfo* rp = reals + blockIdx.x;
+  RecInfo* rc = recs + blockIdx.x;
+  const float* y = curves + (int64_t)blockIdx.x * 256;
+  const int N = rp->N, e_base = rp->e_base, k_top = rc->k_top;
+  int k_s = (-2 * N - e_base + 3) / 4;
+  if (k_s < 0) k_s = 0;
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = (k_s >= k_top) ? 1 : 0;
+  __syncthreads();
+  for (int k = k_s + (int)threadIdx.x; k < k_top; k += blockDim.x) {
+    const double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
+    const double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
+    const double d = s1 - s0;
+    if (!(d > 0.0) || !isfinite(d)) atomicOr(&s_bad, 1);
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (threadIdx.x == 0) k_seed_out[blockIdx.x] = -1;
+    return;
+  }
+  const int64_t off = rp->level_off;
+  for (int k = k_s + (int)threadIdx.x; k < k_top; k += blockDim.x) {
+    const double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
+    const double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
+    A.b[off + k] = s1 - s0;
+  }
+  const int cap = level_capacity(N);
+  for (int k = threadIdx.x; k < cap; k += blockDim.x) A.p[off + k] = 0.0;
+  if (threadIdx.x == 0) {
+    rc->k_seed = k_s;
+    k_seed_out[blockIdx.x] = k_s;
+  }
+}
+
+hipError_t launch_rec_seed_copy(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const double* src,
+                                const int32_t* k_seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_seed_copy, dim3(n_real), dim3(256), 0, s, reals, recs, A, src, k_seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_seed_grid(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const float* curves,
+                                int32_t* k_seed_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_seed_grid, dim3(n_real), dim3(256), 0, s, reals, recs, A, curves, k_seed_out);
+  return hipGetLastError();
 }
 
 hipError_t launch_rec_init(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws, int profile,

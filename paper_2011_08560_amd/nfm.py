@@ -38,7 +38,8 @@ REAL_DTYPE = np.dtype([("rt_count", np.uint64), ("rt_time", np.uint64), ("E_min"
 
 REC_DTYPE = np.dtype([("k_lo", np.int32), ("k_top", np.int32), ("profile", np.int32), ("converged", np.int32),
                       ("iterations", np.int32), ("k_lo_changed", np.int32), ("pl_dE", np.float64),
-                      ("pl_alpha", np.float64), ("flatness", np.float64)], align=True)
+                      ("pl_alpha", np.float64), ("flatness", np.float64), ("k_seed", np.int32),
+                      ("pad", np.int32)], align=True)
 RT_SUMMARY_DTYPE = np.dtype([("tau_pop", np.float64), ("trips", np.uint64), ("n_used", np.int32),
                              ("n_censored", np.int32)], align=True)
 PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
@@ -108,7 +109,30 @@ def lib():
         "nfm_pt_read_exchanges": (i32, [vp, vp]),
         "nfm_rt_stats": (i32, [vp, i32, i32, u64, vp, vp]),
         "nfm_autotune": (i32, [vp, i32, C.c_char_p, vp, i32, C.POINTER(i32), vp]),
+        "nfm_rec_seed": (i32, [vp, vp, vp]),
+        "nfm_rec_seed_grid": (i32, [vp, vp, vp]),
+        "nfm_set_canonical": (i32, [vp, C.c_double]),
+        "nfm_features": (i32, [vp, vp]),
     }
+    f32 = C.c_float
+    sig.update({
+        "nfm_mlp_n_params": (i32, []),
+        "nfm_mlp_workspace_bytes": (i32, [i32, C.POINTER(sz)]),
+        "nfm_mlp_create": (i32, [C.POINTER(vp), i32, vp, sz, C.c_int, vp]),
+        "nfm_mlp_destroy": (None, [vp]),
+        "nfm_mlp_last_error": (C.c_char_p, [vp]),
+        "nfm_mlp_init": (i32, [vp, u64]),
+        "nfm_mlp_set_params": (i32, [vp, vp, vp]),
+        "nfm_mlp_get_params": (i32, [vp, vp, vp]),
+        "nfm_mlp_get_grads": (i32, [vp, vp]),
+        "nfm_mlp_forward": (i32, [vp, vp, i32, vp]),
+        "nfm_mlp_loss_grad": (i32, [vp, vp, vp, vp, i32, vp]),
+        "nfm_mlp_adam": (i32, [vp, f32, f32, f32, f32]),
+        "nfm_mlp_train_step": (i32, [vp, vp, vp, vp, i32, f32]),
+        "nfm_mlp_last_loss": (i32, [vp, vp]),
+        "nfm_mlp_to_bf16": (i32, [vp]),
+        "nfm_mlp_infer_bf16": (i32, [vp, vp, i32, vp]),
+    })
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
@@ -380,7 +404,7 @@ class Batch:
         return out
 
     def rec_set_state(self, r: int, b, p, lnP, lnW, visited, k_lo: int, k_top: int, profile: int = PROFILE_FLAT,
-                      pl_dE: float = 1.0, pl_alpha: float = 0.0):
+                      pl_dE: float = 1.0, pl_alpha: float = 0.0, k_seed: int = -1):
         n = 3 * int(self.Ls[r]) ** 3 // 2 + 1
         arr = [np.zeros(n, np.float64) for _ in range(4)]
         for a, v in zip(arr, (b, p, lnP, lnW)):
@@ -390,6 +414,7 @@ class Batch:
         info = np.zeros(1, REC_DTYPE)
         info["k_lo"], info["k_top"], info["profile"] = k_lo, k_top, profile
         info["pl_dE"], info["pl_alpha"] = pl_dE, pl_alpha
+        info["k_seed"] = k_seed
         self._check(self._lib.nfm_rec_set_state(self.ctx, r, arr[0].ctypes.data, arr[1].ctypes.data,
                                                 arr[2].ctypes.data, arr[3].ctypes.data, vis.ctypes.data,
                                                 info.ctypes.data), "rec_set_state")
@@ -465,3 +490,134 @@ class Batch:
         self._check(self._lib.nfm_rt_stats(self.ctx, r0, count, min_trips, tau.ctypes.data, summ.ctypes.data),
                     "rt_stats")
         return tau, summ[0]
+
+    # learned seeding
+    def rec_seed(self, b_levels, k_seed):
+        """Seeded prior: b_levels (levels_total doubles, by level offset), k_seed per realization
+        (-1 = leave it plain)."""
+        bl = np.ascontiguousarray(b_levels, np.float64)
+        ks = np.ascontiguousarray(k_seed, np.int32)
+        self._check(self._lib.nfm_rec_seed(self.ctx, bl.ctypes.data, ks.ctypes.data), "rec_seed")
+
+    def rec_seed_grid(self, curves) -> np.ndarray:
+        """Seeded prior from device curves (torch float32 [n_real, 256] on this GPU); returns k_seed
+        per realization (-1: rejected, plain start kept)."""
+        ks = np.zeros(self.n_real, np.int32)
+        self._check(self._lib.nfm_rec_seed_grid(self.ctx, C.c_void_p(curves.data_ptr()), ks.ctypes.data),
+                    "rec_seed_grid")
+        return ks
+
+    def set_canonical(self, T: float):
+        self._check(self._lib.nfm_set_canonical(self.ctx, T), "set_canonical")
+
+    def features(self, out=None):
+        """Inputs of the seeding model into a torch float32 [n_real, 81] tensor on this GPU."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_real, 81), dtype=torch.float32, device=self.device)
+        self._check(self._lib.nfm_features(self.ctx, C.c_void_p(out.data_ptr())), "features")
+        return out
+
+
+class Mlp:
+    """The weight-seeding network over a torch-allocated device workspace (nfm_mlp_*)."""
+
+    N_IN, N_OUT = 81, 256
+
+    def __init__(self, batch_max: int = 256, device: int = 0, stream=None):
+        import torch
+        self._lib = lib()
+        self.batch_max = batch_max
+        n = C.c_size_t()
+        st = self._lib.nfm_mlp_workspace_bytes(batch_max, C.byref(n))
+        if st != NFM_OK:
+            raise NfmError(st, "mlp workspace size")
+        self.device = torch.device("cuda", device)
+        self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._ws.data_ptr() + 255) // 256 * 256
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        ctx = C.c_void_p()
+        st = self._lib.nfm_mlp_create(C.byref(ctx), batch_max, C.c_void_p(aligned), n.value, device,
+                                      C.c_void_p(stream.cuda_stream))
+        if st != NFM_OK:
+            raise NfmError(st, "mlp create")
+        self.ctx = ctx
+        self.n_params = int(self._lib.nfm_mlp_n_params())
+
+    def _check(self, st, what):
+        if st != NFM_OK:
+            raise NfmError(st, f"{what}: {self._lib.nfm_mlp_last_error(self.ctx).decode()}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self._lib.nfm_mlp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, seed: int):
+        self._check(self._lib.nfm_mlp_init(self.ctx, seed), "init")
+
+    def set_params(self, params=None, norm=None):
+        p = None if params is None else np.ascontiguousarray(params, np.float32)
+        q = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        self._check(self._lib.nfm_mlp_set_params(self.ctx, None if p is None else p.ctypes.data,
+                                                 None if q is None else q.ctypes.data), "set_params")
+
+    def get_params(self):
+        p = np.zeros(self.n_params, np.float32)
+        q = np.zeros((2, self.N_IN), np.float32)
+        self._check(self._lib.nfm_mlp_get_params(self.ctx, p.ctypes.data, q.ctypes.data), "get_params")
+        return p, q
+
+    def get_grads(self):
+        g = np.zeros(self.n_params, np.float32)
+        self._check(self._lib.nfm_mlp_get_grads(self.ctx, g.ctypes.data), "get_grads")
+        return g
+
+    @staticmethod
+    def _p(t):
+        return C.c_void_p(t.data_ptr())
+
+    def forward(self, x, out=None):
+        import torch
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty((B, self.N_OUT), dtype=torch.float32, device=self.device)
+        self._check(self._lib.nfm_mlp_forward(self.ctx, self._p(x), B, self._p(out)), "forward")
+        return out
+
+    def loss_grad(self, x, t, mask) -> float:
+        loss = C.c_float()
+        self._check(self._lib.nfm_mlp_loss_grad(self.ctx, self._p(x), self._p(t), self._p(mask), x.shape[0],
+                                                C.byref(loss)), "loss_grad")
+        return float(loss.value)
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self._lib.nfm_mlp_adam(self.ctx, lr, beta1, beta2, eps), "adam")
+
+    def train_step(self, x, t, mask, lr=1e-3):
+        self._check(self._lib.nfm_mlp_train_step(self.ctx, self._p(x), self._p(t), self._p(mask), x.shape[0], lr),
+                    "train_step")
+
+    def last_loss(self) -> float:
+        loss = C.c_float()
+        self._check(self._lib.nfm_mlp_last_loss(self.ctx, C.byref(loss)), "last_loss")
+        return float(loss.value)
+
+    def to_bf16(self):
+        self._check(self._lib.nfm_mlp_to_bf16(self.ctx), "to_bf16")
+
+    def infer_bf16(self, x, out=None):
+        import torch
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty((B, self.N_OUT), dtype=torch.float32, device=self.device)
+        self._check(self._lib.nfm_mlp_infer_bf16(self.ctx, self._p(x), B, self._p(out)), "infer_bf16")
+        return out

@@ -1,0 +1,268 @@
+"""GPU parity of the learned start of the weight iteration against the oracle: canonical
+tables, frustration features and histogram bins, the seeded recursion (grid-to-steps
+conversion, weights, update, tables), and the seeding network (FP32 forward, loss and
+gradient, Adam step, BF16 inference).
+
+Tolerances: integer parts exact; features 1e-6 (FP32 storage of FP64 values); the seeded
+recursion 1e-12 relative (FP64, as for the plain one); the network in FP32 against the FP64
+oracle 2e-5 relative normwise for outputs and loss, 1e-4 for gradients (sums over the batch
+in FP32), the Adam step 1e-5; BF16 inference 1e-2 against an FP64 model that rounds weights
+and activations to BF16 at the same points, 6e-2 against the exact FP64 model.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+DSEED, WSEED = 20110856, 0x5EED5EED
+
+
+@pytest.fixture(scope="module")
+def nfm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_08560_amd import nfm as m
+    m.lib()
+    return m
+
+
+def _normwise(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_canonical_tables_and_features(nfm, orc):
+    import torch
+    Ls = [4, 6, 4, 8]
+    b = nfm.Batch(Ls, [64] * len(Ls), DSEED, WSEED, first_real_id=3)
+    b.init_couplings()
+    b.init_spins()
+    b.compute_energies()
+    T = 2.0
+    b.set_canonical(T)
+    for r, L in enumerate(Ls):
+        J = orc.couplings(L, DSEED, 3 + r)
+        K, eb = orc.n_levels(L, J), orc.e_base(L, J)
+        lnw = -np.array([eb + 4 * (K - 2), eb + 4 * (K - 1)], np.float64) / T
+        thr, row0 = orc.build_thresholds(K, lnw, K - 2, K - 1)
+        dthr, drow0 = b.get_thresholds(r)
+        assert drow0 == row0
+        diff = np.argwhere(dthr != thr)
+        assert len(diff) <= 2 and all(abs(int(dthr[i, j]) - int(thr[i, j])) == 1 for i, j in diff)
+        b.set_thresholds(r, thr, row0)     # identical tables for the histogram check
+    b.run_sweeps(30)
+    b.reset_histograms()
+    b.run_sweeps(50)
+    H = b.read_histograms()
+    x = b.features().cpu().numpy()
+    for r, L in enumerate(Ls):
+        J = orc.couplings(L, DSEED, 3 + r)
+        K, eb = orc.n_levels(L, J), orc.e_base(L, J)
+        f = orc.features(L, J)
+        hb = orc.hist_bins(K, eb, L ** 3, H[b.level_offset(r):b.level_offset(r) + K])
+        want = np.concatenate([[L / 12.0], f, hb]).astype(np.float32)
+        assert np.allclose(x[r], want, rtol=1e-6, atol=1e-7), (r, x[r] - want)
+        assert abs(x[r, 17:].sum() - 1.0) < 1e-5
+    b.close()
+    assert torch.cuda.is_available()
+
+
+def _seeded_batch(nfm, orc, L, n_real, first):
+    b = nfm.Batch([L] * n_real, [64] * n_real, DSEED, WSEED, first_real_id=first)
+    b.init_couplings()
+    b.init_spins()
+    b.compute_energies()
+    b.rec_init(0)
+    return b
+
+
+def test_seed_grid_matches_oracle_and_rejects(nfm, orc):
+    import torch
+    L, n_real, first = 6, 3, 30
+    b = _seeded_batch(nfm, orc, L, n_real, first)
+    e = -2.0 + 2.0 * np.arange(256) / 255.0
+    curves = np.stack([0.9 * e - 0.05 * e ** 2, 1.1 * e, -0.5 * e]).astype(np.float32)   # last one decreasing
+    ks = b.rec_seed_grid(torch.tensor(curves, device="cuda"))
+    for r in range(n_real):
+        J = orc.couplings(L, DSEED, first + r)
+        K, eb = orc.n_levels(L, J), orc.e_base(L, J)
+        k_top = (-eb + 3) // 4
+        bref = np.zeros(K)
+        k_ref = orc.seed_from_grid(L ** 3, eb, k_top, curves[r], bref)
+        assert ks[r] == k_ref
+        st = b.rec_get_state(r)
+        assert st["info"]["k_seed"] == k_ref
+        if k_ref >= 0:
+            assert _normwise(st["b"][k_ref:k_top], bref[k_ref:k_top]) <= 1e-12
+            assert not st["p"].any()
+            # weights and table extend down to k_seed
+            S, lnP, lnW = orc.rec_weights_ext(K, eb, int(st["info"]["k_lo"]), k_top, k_ref, 0, 1.0, 0.0, st["b"])
+            lo = min(k_ref, int(st["info"]["k_lo"]))
+            assert _normwise(st["lnW"][lo:k_top + 1], lnW[lo:k_top + 1]) <= 1e-12
+            thr, row0 = b.get_thresholds(r)
+            thr_ref, row0_ref = orc.build_thresholds(K, lnW[lo:k_top + 1], lo, k_top)
+            assert row0 == row0_ref
+            d = np.argwhere(thr != thr_ref)
+            assert len(d) <= 3
+        else:
+            assert not st["b"].any()
+    b.close()
+
+
+@pytest.mark.parametrize("profile,dE,alpha", [(0, 1.0, 0.0), (1, 1.0, -1.0)])
+def test_seeded_iterations_lockstep_with_oracle(nfm, orc, profile, dE, alpha):
+    """Seeded weight iteration on the device against the oracle, iteration by iteration."""
+    L, n_real, W, n_it, n_sw, first = 4, 2, 64, 4, 120, 60
+    b = nfm.Batch([L] * n_real, [W] * n_real, DSEED, WSEED, first_real_id=first)
+    b.init_couplings()
+    b.init_spins()
+    b.compute_energies()
+    b.rec_init(profile, dE, alpha)
+    rzs = [orc.make_realization(L, DSEED, first + r, WSEED, W) for r in range(n_real)]
+    sts = [orc.recursion_init(rz) for rz in rzs]
+    rng = np.random.default_rng(4)
+    bl = np.zeros(b.levels_total)
+    kseeds = []
+    for r, (rz, st) in enumerate(zip(rzs, sts)):
+        k_s = max(0, (-2 * rz.N - rz.eb + 3) // 4)
+        steps = rng.uniform(0.5, 1.5, rz.k_top - k_s)
+        st.b[k_s:rz.k_top] = steps
+        bl[b.level_offset(r) + k_s:b.level_offset(r) + rz.k_top] = steps
+        kseeds.append(k_s)
+    b.rec_seed(bl, np.array(kseeds, np.int32))
+    for it in range(n_it):
+        for r, (rz, st) in enumerate(zip(rzs, sts)):
+            k_low = min(kseeds[r], st.k_lo)
+            S, lnP, lnW = orc.rec_weights_ext(rz.K, rz.eb, st.k_lo, st.k_top, k_low, profile, dE, alpha, st.b)
+            thr, row0 = orc.build_thresholds(rz.K, lnW[k_low:st.k_top + 1], k_low, st.k_top)
+            dthr, drow0 = b.get_thresholds(r)
+            assert drow0 == row0
+            assert np.sum(dthr != thr) <= 3
+            b.set_thresholds(r, thr, row0)
+            st.tab = (lnW, lnP, k_low)
+        b.run_sweeps(n_sw)
+        H = b.read_histograms()
+        info = b.rec_update(0.5)
+        for r, (rz, st) in enumerate(zip(rzs, sts)):
+            lnW, lnP, k_low = st.tab
+            thr, row0 = orc.build_thresholds(rz.K, lnW[k_low:st.k_top + 1], k_low, st.k_top)
+            Hr, _ = orc.sample(rz, thr, row0, rz.eb + 4 * st.k_lo, 0, n_sw)
+            off = b.level_offset(r)
+            assert np.array_equal(H[off:off + rz.K], Hr), (it, r)
+            k_min = (int(rz.w["E_min"].min()) - rz.eb) // 4
+            st.k_lo, flat = orc.rec_update_ext(rz.K, st.k_lo, st.k_top, k_low, True, min(k_min, st.k_lo), lnW, lnP,
+                                               Hr, st.b, st.p, st.visited)
+            assert info["k_lo"][r] == st.k_lo
+            assert abs(info["flatness"][r] - flat) <= 1e-12 * max(flat, 1e-300)
+            d = b.rec_get_state(r)
+            sl = slice(min(kseeds[r], st.k_lo), st.k_top)
+            assert _normwise(d["b"][sl], st.b[sl]) <= 1e-12
+            assert _normwise(d["p"][sl], st.p[sl]) <= 1e-12 if st.p[sl].any() else not d["p"][sl].any()
+    b.close()
+
+
+# ------------------------------------------------------------------ the network
+
+def _bf16(x):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _forward_bf16_ref(mlp_mod, theta, norm, X):
+    P = mlp_mod.unflatten(theta)
+    A = _bf16(mlp_mod.normalize(X, norm).astype(np.float32))
+    for k in range(3):
+        Z = A @ _bf16(P[f"W{k}"].astype(np.float32)) + P[f"b{k}"]
+        A = _bf16(mlp_mod.gelu(Z).astype(np.float32))
+    return A @ _bf16(P["W3"].astype(np.float32)) + P["b3"]
+
+
+@pytest.fixture(scope="module")
+def net(nfm):
+    import torch
+    from oracle import mlp as M
+    rng = np.random.default_rng(11)
+    m = nfm.Mlp(batch_max=96)
+    m.init(1234)
+    theta, norm = m.get_params()
+    assert not theta.reshape(-1)[M.D_IN * M.HID:M.D_PAD * M.HID].any(), "padding rows zero"
+    norm = np.stack([rng.normal(0, 1, M.D_IN), rng.uniform(0.5, 2.0, M.D_IN)]).astype(np.float32)
+    theta = theta.copy()
+    theta[-256:] = rng.normal(0, 0.1, 256)                  # nonzero output bias
+    for name in ("b0", "b1", "b2"):                          # and hidden biases
+        P = M.unflatten(np.arange(M.N_PARAM))
+        idx = P[name].astype(int)
+        theta[idx] = rng.normal(0, 0.1, len(idx))
+    m.set_params(theta, norm)
+    B = 83                                                   # not a multiple of 16
+    X = rng.normal(0, 1, (B, M.D_IN)).astype(np.float32)
+    T = rng.normal(0, 1, (B, M.D_OUT)).astype(np.float32)
+    Mk = (rng.random((B, M.D_OUT)) < 0.6).astype(np.float32)
+    dev = {k: torch.tensor(v, device="cuda") for k, v in (("X", X), ("T", T), ("M", Mk))}
+    yield m, M, theta.astype(np.float64), norm.astype(np.float64), X, T, Mk, dev
+    m.close()
+
+
+def test_mlp_forward_loss_grad(net):
+    m, M, theta, norm, X, T, Mk, dev = net
+    Y = m.forward(dev["X"]).cpu().numpy()
+    Yref = M.forward(theta, norm, X.astype(np.float64))
+    assert _normwise(Y, Yref) <= 2e-5
+    loss = m.loss_grad(dev["X"], dev["T"], dev["M"])
+    Lref, gref = M.loss_and_grad(theta, norm, X.astype(np.float64), T.astype(np.float64), Mk.astype(np.float64))
+    assert abs(loss - Lref) <= 2e-5 * Lref
+    g = m.get_grads().astype(np.float64)
+    P, Pr = M.unflatten(g), M.unflatten(gref)
+    for name in Pr:
+        assert _normwise(P[name], Pr[name]) <= 1e-4, name
+    assert not P["W0"][M.D_IN:].any()
+
+
+def test_mlp_adam_step(net):
+    m, M, theta, norm, X, T, Mk, dev = net
+    m.set_params(theta.astype(np.float32))            # fresh optimizer state
+    m.loss_grad(dev["X"], dev["T"], dev["M"])
+    g = m.get_grads().astype(np.float64)
+    m.adam(lr=1e-3)
+    th1, _ = m.get_params()
+    ref = theta.copy()
+    mm, vv = np.zeros_like(ref), np.zeros_like(ref)
+    M.adam_step(ref, g, mm, vv, 1, 1e-3)
+    assert np.max(np.abs(th1 - ref)) <= 1e-5 * 1e-3 + 1e-7
+    # a second step from the device gradient at the new point
+    m.loss_grad(dev["X"], dev["T"], dev["M"])
+    g2 = m.get_grads().astype(np.float64)
+    m.adam(lr=1e-3)
+    th2, _ = m.get_params()
+    M.adam_step(ref, g2, mm, vv, 2, 1e-3)
+    assert np.max(np.abs(th2 - ref)) <= 3e-6
+    m.set_params(theta.astype(np.float32))
+
+
+def test_mlp_bf16_inference(net):
+    m, M, theta, norm, X, T, Mk, dev = net
+    m.to_bf16()
+    Y = m.infer_bf16(dev["X"]).cpu().numpy()
+    Yb = _forward_bf16_ref(M, theta, norm, X.astype(np.float64))
+    Y64 = M.forward(theta, norm, X.astype(np.float64))
+    assert _normwise(Y, Yb) <= 1e-2
+    assert _normwise(Y, Y64) <= 6e-2
+
+
+def test_mlp_training_reduces_loss(net):
+    m, M, theta, norm, X, T, Mk, dev = net
+    import torch
+    m.set_params(theta.astype(np.float32))
+    rng = np.random.default_rng(2)
+    # a learnable target: a fixed random linear map of the inputs
+    Wt = rng.normal(0, 0.3, (M.D_IN, M.D_OUT)).astype(np.float32)
+    Tl = torch.tensor(X @ Wt, device="cuda")
+    ones = torch.ones_like(Tl)
+    l0 = m.loss_grad(dev["X"], Tl, ones)
+    for _ in range(200):
+        m.train_step(dev["X"], Tl, ones, lr=2e-3)
+    l1 = m.last_loss()
+    assert l1 < 0.2 * l0, (l0, l1)
+    m.set_params(theta.astype(np.float32))
