@@ -352,9 +352,16 @@ nfm_status nfm_rt_stats(nfm_ctx* ctx, int32_t r0, int32_t count, uint64_t min_tr
  *   Weights, tables and bounds are rebuilt. Needs nfm_rec_init. host_k_seed = -1: unchanged.
  * nfm_rec_seed_grid: the same from curves y (device, n_real x 256 floats) with y_j = [S(E) -
  *   S(E_top)]/N on e_j = -2 + 2j/255: S(k) = N y(E_k/N), linear between grid points, y_255
- *   above; b(k) = S(k+1) - S(k) on [k_s, k_top), k_s = lowest level with E >= -2N. A curve with
- *   a step that is not positive and finite is rejected and the realization keeps its plain
- *   start. host_k_seed (optional, n_real) receives k_s or -1. */
+ *   above; b(k) = max(S(k+1) - S(k), 0) on [k_s, k_top), k_s = the lowest level with E >= -2N
+ *   (a decrease of the curve, e.g. its noise where the true steps are near zero at the top,
+ *   gives a flat step). A curve with a step that is not finite, or with no positive step, is
+ *   rejected and the realization keeps its plain start. host_k_seed (optional, n_real)
+ *   receives k_s or -1. */
+/* nfm_rec_targets: training targets from the current estimate, per realization 256 floats each
+ * into dev_y and dev_mask (device): y_j = S(e_j N)/N on the grid e_j = -2 + 2j/255, S linear
+ * between levels with S(k_top) = 0 (and S(k_top) above E(k_top)); mask 1 where e_j N >= E(k_lo),
+ * else 0 with y = 0. */
+nfm_status nfm_rec_targets(nfm_ctx* ctx, float* dev_y, float* dev_mask);
 nfm_status nfm_set_canonical(nfm_ctx* ctx, double T);
 nfm_status nfm_features(nfm_ctx* ctx, float* dev_x);
 nfm_status nfm_rec_seed(nfm_ctx* ctx, const double* host_b, const int32_t* host_k_seed);

@@ -451,9 +451,11 @@ void orc_rec_update_ext(int32_t K, int32_t k_lo_used, int32_t k_top, int32_t k_l
 
 /* Seed of the DOS steps from a curve y_j = [S(E) - S(E_top)]/N on the energy grid
  * e_j = -2 + 2j/255 (j = 0..255): S(k) = N y(E_k/N), linear between grid points and y_255
- * above the grid; b(k) = S(k+1) - S(k) on [k_s, k_top), k_s the lowest level with
- * E_k >= -2N. Returns k_s, or -1 (and leaves b alone) if any step is not positive and
- * finite: the curve is then rejected and the plain start is kept.                  */
+ * above the grid; steps b(k) = max(S(k+1) - S(k), 0) on [k_s, k_top), k_s the lowest level
+ * with E >= -2N (a decrease of the curve, such as its noise where the true steps are near zero
+ * at the top, or anything below the ground state, gives a flat step). Returns k_s and fills b,
+ * or returns -1 (b untouched) when a step is not finite or no step is positive: the curve is
+ * then rejected and the plain start is kept.                                      */
 static double seed_curve(const float* y, double e) {
   double t = (e + 2.0) * 127.5;
   if (t <= 0.0) return (double)y[0];
@@ -463,20 +465,25 @@ static double seed_curve(const float* y, double e) {
   return (double)y[j] + f * ((double)y[j + 1] - (double)y[j]);
 }
 
+static double seed_step(int32_t N, int32_t e_base, const float* y, int32_t k) {
+  double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
+  double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
+  return s1 - s0;
+}
+
 int32_t orc_seed_from_grid(int32_t N, int32_t e_base, int32_t k_top, const float* y, double* b) {
   int32_t k_s = (-2 * N - e_base + 3) / 4;   /* ceil((-2N - e_base)/4), -2N - e_base >= 0 */
   if (k_s < 0) k_s = 0;
-  if (k_s >= k_top) return -1;
+  double total = 0.0;
   for (int32_t k = k_s; k < k_top; ++k) {
-    double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
-    double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
-    double d = s1 - s0;
-    if (!(d > 0.0) || !isfinite(d)) return -1;
+    double d = seed_step(N, e_base, y, k);
+    if (!isfinite(d)) return -1;
+    if (d > 0.0) total += d;
   }
+  if (!(total > 0.0)) return -1;
   for (int32_t k = k_s; k < k_top; ++k) {
-    double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
-    double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
-    b[k] = s1 - s0;
+    double d = seed_step(N, e_base, y, k);
+    b[k] = d > 0.0 ? d : 0.0;
   }
   return k_s;
 }

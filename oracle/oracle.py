@@ -255,7 +255,7 @@ def rec_update_ext(K, k_lo_used, k_top, k_low_used, seeded, k_min_seen, lnW_used
 
 
 def seed_from_grid(N, eb, k_top, y, b):
-    """Fill b from a 256-point curve (in place); returns k_s or -1 (rejected)."""
+    """Fill b on [k_s, k_top) from a 256-point curve (in place); returns k_s or -1 (rejected)."""
     return int(lib().orc_seed_from_grid(N, eb, k_top, np.ascontiguousarray(y, np.float32), b))
 
 
@@ -463,3 +463,26 @@ def rt_population(taus):
     t = np.asarray(taus, np.float64)
     t = t[~np.isnan(t)]
     return float(t.sum() / len(t)) if len(t) else float("nan")
+
+
+# --------------------------------------------------------------------------- seeding targets
+
+def rec_targets(N, eb, k_lo, k_top, S):
+    """Targets of the seeding model from an estimate S (by level, S(k_top) = 0): y_j = S(e_j N)/N on
+    e_j = -2 + 2j/255, linear between levels; mask 1 where e_j N >= E(k_lo)."""
+    y = np.zeros(256)
+    m = np.zeros(256)
+    E_lo, E_top = eb + 4 * k_lo, eb + 4 * k_top
+    for j in range(256):
+        E = (-2.0 + 2.0 * j / 255.0) * N
+        if E < E_lo:
+            continue
+        if E >= E_top:
+            v = S[k_top]
+        else:
+            t = (E - eb) / 4.0
+            k = min(max(int(np.floor(t)), k_lo), k_top - 1)
+            v = S[k] + (t - k) * (S[k + 1] - S[k])
+        y[j] = v / N
+        m[j] = 1.0
+    return y, m

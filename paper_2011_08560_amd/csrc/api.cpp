@@ -1176,6 +1176,16 @@ nfm_status nfm_rec_seed_grid(nfm_ctx* c, const float* dev_curves, int32_t* host_
   return pull_reals(c);
 }
 
+nfm_status nfm_rec_targets(nfm_ctx* c, float* dev_y, float* dev_mask) {
+  NFM_GUARD(c);
+  if (!c->rec_ready) return fail(c, NFM_ESTATE, "rec_targets: call nfm_rec_init first");
+  if (!dev_y || !dev_mask) return fail(c, NFM_EINVAL, "rec_targets: null pointer");
+  hipError_t e = nfm::launch_rec_targets(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), dev_y, dev_mask,
+                                         c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("rec_targets: ") + hipGetErrorString(e));
+  return NFM_OK;
+}
+
 nfm_status nfm_set_canonical(nfm_ctx* c, double T) {
   NFM_GUARD(c);
   if (!c->couplings) return fail(c, NFM_ESTATE, "set_canonical: couplings not set");

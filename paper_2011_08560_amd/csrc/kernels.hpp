@@ -46,6 +46,8 @@ hipError_t launch_rec_weights(RealInfo* reals, RecInfo* recs, int n_real, RecArr
                               int set_bounds, hipStream_t s);
 hipError_t launch_rec_update(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, WalkerState ws,
                              unsigned long long* hist, uint32_t* tables, double f_tol, hipStream_t s);
+hipError_t launch_rec_targets(const RealInfo* reals, const RecInfo* recs, int n_real, RecArrays A, float* y, float* mask,
+                              hipStream_t s);
 hipError_t launch_rec_seed_copy(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const double* src,
                                 const int32_t* k_seed, hipStream_t s);
 hipError_t launch_rec_seed_grid(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const float* curves,

@@ -230,9 +230,10 @@ __global__ void k_rec_seed_copy(RealInfo* __restrict__ reals, RecInfo* __restric
 }
 
 // Seeded prior from a curve y_j = [S(E) - S(E_top)]/N on the grid e_j = -2 + 2j/255 (256 floats
-// per realization): S(k) = N y(E_k/N), linear between grid points, y_255 above; b(k) = S(k+1) -
-// S(k) on [k_s, k_top), k_s = lowest level with E >= -2N. A curve with a step that is not
-// positive and finite is rejected (the realization keeps its plain start; k_seed_out = -1).
+// per realization): S(k) = N y(E_k/N), linear between grid points, y_255 above; b(k) =
+// max(S(k+1) - S(k), 0) on [k_s, k_top), k_s = the lowest level with E >= -2N. A curve with a
+// step that is not finite, or without a positive step, is rejected (plain start kept;
+// k_seed_out = -1).
 __device__ __forceinline__ double seed_curve(const float* y, double e) {
   const double t = (e + 2.0) * 127.5;
   if (t <= 0.0) return (double)y[0];
@@ -240,6 +241,12 @@ __device__ __forceinline__ double seed_curve(const float* y, double e) {
   const int j = (int)floor(t);
   const double f = t - (double)j;
   return (double)y[j] + f * ((double)y[j + 1] - (double)y[j]);
+}
+
+__device__ __forceinline__ double seed_step(int N, int e_base, const float* y, int k) {
+  const double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
+  const double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
+  return s1 - s0;
 }
 
 __global__ void k_rec_seed_grid(RealInfo* __restrict__ reals, RecInfo* __restrict__ recs, RecArrays A,
@@ -251,24 +258,29 @@ __global__ void k_rec_seed_grid(RealInfo* __restrict__ reals, RecInfo* __restric
   int k_s = (-2 * N - e_base + 3) / 4;
   if (k_s < 0) k_s = 0;
   __shared__ int s_bad;
-  if (threadIdx.x == 0) s_bad = (k_s >= k_top) ? 1 : 0;
+  __shared__ double s_pos[256];
+  if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
+  double pos = 0.0;
   for (int k = k_s + (int)threadIdx.x; k < k_top; k += blockDim.x) {
-    const double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
-    const double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
-    const double d = s1 - s0;
-    if (!(d > 0.0) || !isfinite(d)) atomicOr(&s_bad, 1);
+    const double d = seed_step(N, e_base, y, k);
+    if (!isfinite(d)) atomicOr(&s_bad, 1);
+    if (d > 0.0) pos += d;
   }
+  s_pos[threadIdx.x] = pos;
   __syncthreads();
-  if (s_bad) {
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s_pos[threadIdx.x] += s_pos[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (s_bad || !(s_pos[0] > 0.0)) {
     if (threadIdx.x == 0) k_seed_out[blockIdx.x] = -1;
     return;
   }
   const int64_t off = rp->level_off;
   for (int k = k_s + (int)threadIdx.x; k < k_top; k += blockDim.x) {
-    const double s0 = (double)N * seed_curve(y, (double)(e_base + 4 * k) / (double)N);
-    const double s1 = (double)N * seed_curve(y, (double)(e_base + 4 * (k + 1)) / (double)N);
-    A.b[off + k] = s1 - s0;
+    const double d = seed_step(N, e_base, y, k);
+    A.b[off + k] = d > 0.0 ? d : 0.0;
   }
   const int cap = level_capacity(N);
   for (int k = threadIdx.x; k < cap; k += blockDim.x) A.p[off + k] = 0.0;
@@ -276,6 +288,44 @@ __global__ void k_rec_seed_grid(RealInfo* __restrict__ reals, RecInfo* __restric
     rc->k_seed = k_s;
     k_seed_out[blockIdx.x] = k_s;
   }
+}
+
+// Training targets from the current estimate: on the grid e_j = -2 + 2j/255, y_j = S(e_j N) / N
+// with S linear between levels (S(k_top) = 0), mask 1 where e_j N >= E(k_lo) (the estimate is
+// defined there), 0 and y = 0 below.
+__global__ void k_rec_targets(const RealInfo* __restrict__ reals, const RecInfo* __restrict__ recs, RecArrays A,
+                              float* __restrict__ y, float* __restrict__ mask) {
+  const RealInfo ri = reals[blockIdx.x];
+  const RecInfo rc = recs[blockIdx.x];
+  const double* S = A.S + ri.level_off;
+  const int j = threadIdx.x;  // 256 threads
+  const double N = (double)ri.N;
+  const double E = (-2.0 + 2.0 * (double)j / 255.0) * N;
+  const double E_lo = (double)(ri.e_base + 4 * rc.k_lo), E_top = (double)(ri.e_base + 4 * rc.k_top);
+  float yv = 0.f, mv = 0.f;
+  if (E >= E_lo) {
+    double v;
+    if (E >= E_top) {
+      v = S[rc.k_top];
+    } else {
+      const double t = (E - (double)ri.e_base) / 4.0;
+      int k = (int)floor(t);
+      if (k < rc.k_lo) k = rc.k_lo;
+      if (k > rc.k_top - 1) k = rc.k_top - 1;
+      const double f = t - (double)k;
+      v = S[k] + f * (S[k + 1] - S[k]);
+    }
+    yv = (float)(v / N);
+    mv = 1.f;
+  }
+  y[(int64_t)blockIdx.x * 256 + j] = yv;
+  mask[(int64_t)blockIdx.x * 256 + j] = mv;
+}
+
+hipError_t launch_rec_targets(const RealInfo* reals, const RecInfo* recs, int n_real, RecArrays A, float* y, float* mask,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_targets, dim3(n_real), dim3(256), 0, s, reals, recs, A, y, mask);
+  return hipGetLastError();
 }
 
 hipError_t launch_rec_seed_copy(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, const double* src,

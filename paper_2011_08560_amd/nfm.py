@@ -112,6 +112,7 @@ def lib():
         "nfm_rec_seed": (i32, [vp, vp, vp]),
         "nfm_rec_seed_grid": (i32, [vp, vp, vp]),
         "nfm_set_canonical": (i32, [vp, C.c_double]),
+        "nfm_rec_targets": (i32, [vp, vp, vp]),
         "nfm_features": (i32, [vp, vp]),
     }
     f32 = C.c_float
@@ -506,6 +507,15 @@ class Batch:
         self._check(self._lib.nfm_rec_seed_grid(self.ctx, C.c_void_p(curves.data_ptr()), ks.ctypes.data),
                     "rec_seed_grid")
         return ks
+
+    def rec_targets(self):
+        """(y, mask) torch float32 [n_real, 256] on this GPU from the current estimate."""
+        import torch
+        y = torch.empty((self.n_real, 256), dtype=torch.float32, device=self.device)
+        m = torch.empty_like(y)
+        self._check(self._lib.nfm_rec_targets(self.ctx, C.c_void_p(y.data_ptr()), C.c_void_p(m.data_ptr())),
+                    "rec_targets")
+        return y, m
 
     def set_canonical(self, T: float):
         self._check(self._lib.nfm_set_canonical(self.ctx, T), "set_canonical")

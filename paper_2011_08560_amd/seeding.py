@@ -1,0 +1,216 @@
+"""Learned start of the weight iteration: data, training and the paired evaluation.
+
+The weight iteration of Sec. II (Muller, Schnabel, Janke) starts from W = 1 and needs several
+rounds before the walkers reach the lowest energies and the histogram flattens. Here a small
+network guesses ln Omega(E) of a realization from its couplings and a short T = 2 canonical run;
+the guess seeds the recursion as a prior on the DOS steps (nfm_rec_seed_grid), and the
+recursion remains the judge. Every step runs in the library's kernels: the canonical run, the
+features, the recursion, the targets, the network's training (FP32) and inference (BF16); torch
+only holds device tensors and shuffles minibatches.
+
+    python -m paper_2011_08560_amd.seeding --train-L 6 8 10 --train-real 16384 \
+        --eval-L 10 --eval-real 2048
+
+trains on realizations of the listed sizes (ids from 0), evaluates on fresh realizations (ids
+from 10^6) with and without the seed under the same seeds, sweeps per round and flatness
+tolerance, and prints one JSON line with the iterations to converge of both arms.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import nfm
+
+DSEED, WSEED = 20110856, 0x0C5C5C5
+EVAL_FIRST_ID = 1_000_000
+
+
+def make_batch(Ls, walkers=64, first_real_id=0, disorder_seed=DSEED, walker_seed=WSEED):
+    b = nfm.Batch(list(Ls), [walkers] * len(Ls), disorder_seed, walker_seed, first_real_id=first_real_id)
+    b.init_couplings()
+    b.init_spins()
+    b.compute_energies()
+    return b
+
+
+def canonical_features(b, T=2.0, burn=100, sweeps=1000):
+    """Short canonical run at temperature T (burn-in, then the measured sweeps) and the model's
+    inputs from the couplings and that run's histogram. The walkers are then drawn afresh (the
+    same initial spins), so that the weight iteration starts as it would without the run: from
+    random states, which are in equilibrium under its first weights (W = 1)."""
+    b.set_canonical(T)
+    b.run_sweeps(burn)
+    b.reset_histograms()
+    b.run_sweeps(sweeps)
+    x = b.features()
+    b.reset_histograms()
+    b.init_spins()
+    b.compute_energies()
+    return x
+
+
+def iterate(b, n_sweeps, f_tol=0.5, n_max=50, profile=(0, 1.0, 0.0), initialized=False, therm=0.1):
+    """Weight iterations until every realization has converged once or n_max rounds: each round
+    runs therm * n_sweeps sweeps under the new weights before its n_sweeps measured sweeps (the
+    update reads the histogram as equilibrium data). Returns the round (1-based) at which each
+    realization first converged; n_max + 1 = censored."""
+    if not initialized:
+        b.rec_init(*profile)
+    first = np.full(b.n_real, n_max + 1, np.int64)
+    n_therm = int(round(therm * n_sweeps))
+    for it in range(1, n_max + 1):
+        if n_therm:
+            b.run_sweeps(n_therm)
+            b.reset_histograms()
+        b.run_sweeps(n_sweeps)
+        info = b.rec_update(f_tol)
+        newly = (info["converged"] == 1) & (first > n_max)
+        first[newly] = it
+        if (first <= n_max).all():
+            break
+    return first
+
+
+def converged_targets(b, first, n_max):
+    """Targets of the realizations that converged (the rest are masked out entirely)."""
+    y, m = b.rec_targets()
+    ok = np.asarray(first <= n_max)
+    import torch
+    m = m * torch.tensor(ok.astype(np.float32), device=m.device)[:, None]
+    return y, m, ok
+
+
+def feature_norm(x):
+    """Per-input mean and spread of the training inputs (spread floored for constant inputs)."""
+    mean = x.mean(dim=0)
+    sd = x.std(dim=0).clamp_min(1e-3)
+    return np.stack([mean.cpu().numpy(), sd.cpu().numpy()]).astype(np.float32)
+
+
+def train(mlp, x, y, mask, epochs=50, batch=256, lr=1e-3, seed=0, val_frac=0.1, log=None):
+    """Adam on the masked MSE, minibatches of `batch` realizations, a held-out fraction of
+    realizations for the validation loss. Returns (train losses per epoch, validation loss)."""
+    import torch
+    n = x.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(n, generator=g)
+    n_val = int(round(val_frac * n)) if n >= 20 else 0
+    val, tr = perm[:n_val].to(x.device), perm[n_val:].to(x.device)
+    mlp.set_params(norm=feature_norm(x[tr]))
+    losses = []
+    for ep in range(epochs):
+        order = tr[torch.randperm(len(tr), generator=g).to(x.device)]
+        tot, cnt = 0.0, 0
+        for s in range(0, len(order), batch):
+            idx = order[s:s + batch]
+            if len(idx) == 0:
+                continue
+            xb, yb, mb = x[idx].contiguous(), y[idx].contiguous(), mask[idx].contiguous()
+            mlp.train_step(xb, yb, mb, lr=lr)
+            tot += mlp.last_loss() * len(idx)
+            cnt += len(idx)
+        losses.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep}: loss {losses[-1]:.4g}")
+    val_loss = None
+    if n_val:
+        vals = []
+        for s in range(0, n_val, batch):
+            idx = val[s:s + batch]
+            vals.append(mlp.loss_grad(x[idx].contiguous(), y[idx].contiguous(), mask[idx].contiguous()) * len(idx))
+        val_loss = sum(vals) / n_val
+    return losses, val_loss
+
+
+def generate(Ls, n_per_L, n_sweeps, f_tol, n_max, chunk=4096, first_id=0, log=None):
+    """Training data: per realization the model's inputs and the converged estimate's targets."""
+    import torch
+    xs, ys, ms = [], [], []
+    stats = {}
+    rid = first_id
+    for L in Ls:
+        done = 0
+        conv = 0
+        while done < n_per_L:
+            n = min(chunk, n_per_L - done)
+            b = make_batch([L] * n, first_real_id=rid)
+            x = canonical_features(b)
+            first = iterate(b, n_sweeps, f_tol, n_max)
+            y, m, ok = converged_targets(b, first, n_max)
+            xs.append(x)
+            ys.append(y)
+            ms.append(m)
+            conv += int(ok.sum())
+            b.close()
+            done += n
+            rid += n
+        stats[L] = {"realizations": n_per_L, "converged": conv}
+        if log:
+            log(f"L={L}: {conv}/{n_per_L} converged within {n_max} rounds of {n_sweeps} sweeps")
+    return torch.cat(xs), torch.cat(ys), torch.cat(ms), stats
+
+
+def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID):
+    """Paired comparison on fresh realizations: the same seeds, the same canonical run, then the
+    plain start against the seeded one. Returns the rounds to converge of both arms."""
+    plain = make_batch([L] * n_real, first_real_id=first_id)
+    seeded = make_batch([L] * n_real, first_real_id=first_id)
+    canonical_features(plain)
+    x = canonical_features(seeded)
+    mlp.to_bf16()
+    curves = mlp.infer_bf16(x)
+    seeded.rec_init(0, 1.0, 0.0)
+    k_seed = seeded.rec_seed_grid(curves)
+    it_plain = iterate(plain, n_sweeps, f_tol, n_max)
+    it_seed = iterate(seeded, n_sweeps, f_tol, n_max, initialized=True)
+    plain.close()
+    seeded.close()
+    return it_plain, it_seed, k_seed
+
+
+def summary(it_plain, it_seed, k_seed, n_max):
+    def arm(it):
+        c = it > n_max
+        return {"mean": float(it.mean()), "median": float(np.median(it)), "censored": int(c.sum())}
+    return {"plain": arm(it_plain), "seeded": arm(it_seed), "seed_rejected": int((k_seed < 0).sum()),
+            "fewer": int((it_seed < it_plain).sum()), "more": int((it_seed > it_plain).sum()),
+            "paired_mean_gain": float((it_plain - it_seed).mean())}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-L", type=int, nargs="+", default=[6, 8, 10])
+    ap.add_argument("--train-real", type=int, default=16384, help="training realizations in all")
+    ap.add_argument("--eval-L", type=int, default=10)
+    ap.add_argument("--eval-real", type=int, default=2048)
+    ap.add_argument("--sweeps", type=int, default=10_000, help="sweeps per round of the weight iteration")
+    ap.add_argument("--f-tol", type=float, default=0.5)
+    ap.add_argument("--n-max", type=int, default=50)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=7)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
+    per_L = int(math.ceil(args.train_real / len(args.train_L)))
+    x, y, m, stats = generate(args.train_L, per_L, args.sweeps, args.f_tol, args.n_max, log=log)
+    mlp = nfm.Mlp(batch_max=256)
+    mlp.init(args.seed)
+    losses, val = train(mlp, x, y, m, epochs=args.epochs, lr=args.lr, seed=args.seed, log=log)
+    it_p, it_s, ks = evaluate(mlp, args.eval_L, args.eval_real, args.sweeps, args.f_tol, args.n_max)
+    out = {"train": {"L": args.train_L, "per_L": stats, "final_loss": losses[-1], "val_loss": val},
+           "eval": {"L": args.eval_L, "realizations": args.eval_real,
+                    **summary(it_p, it_s, ks, args.n_max)},
+           "sweeps_per_round": args.sweeps, "f_tol": args.f_tol, "n_max": args.n_max,
+           "wall_s": time.time() - t0}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

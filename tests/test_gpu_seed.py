@@ -81,19 +81,22 @@ def test_seed_grid_matches_oracle_and_rejects(nfm, orc):
     L, n_real, first = 6, 3, 30
     b = _seeded_batch(nfm, orc, L, n_real, first)
     e = -2.0 + 2.0 * np.arange(256) / 255.0
-    curves = np.stack([0.9 * e - 0.05 * e ** 2, 1.1 * e, -0.5 * e]).astype(np.float32)   # last one decreasing
+    # an increasing curve, one that turns down below e = -1.2 (flat steps below), a decreasing one
+    curves = np.stack([0.9 * e - 0.05 * e ** 2, np.where(e >= -1.2, 1.1 * e, 1.1 * (-2.4 - e)),
+                       -0.5 * e]).astype(np.float32)
     ks = b.rec_seed_grid(torch.tensor(curves, device="cuda"))
     for r in range(n_real):
         J = orc.couplings(L, DSEED, first + r)
         K, eb = orc.n_levels(L, J), orc.e_base(L, J)
         k_top = (-eb + 3) // 4
+        st = b.rec_get_state(r)
         bref = np.zeros(K)
         k_ref = orc.seed_from_grid(L ** 3, eb, k_top, curves[r], bref)
         assert ks[r] == k_ref
-        st = b.rec_get_state(r)
         assert st["info"]["k_seed"] == k_ref
         if k_ref >= 0:
             assert _normwise(st["b"][k_ref:k_top], bref[k_ref:k_top]) <= 1e-12
+            assert np.array_equal(st["b"][k_ref:k_top] == 0, bref[k_ref:k_top] == 0)
             assert not st["p"].any()
             # weights and table extend down to k_seed
             S, lnP, lnW = orc.rec_weights_ext(K, eb, int(st["info"]["k_lo"]), k_top, k_ref, 0, 1.0, 0.0, st["b"])

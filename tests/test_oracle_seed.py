@@ -9,7 +9,7 @@ Independent facts used:
     cube product, so every frustration statistic is unchanged;
   * cubes always have an even number of frustrated faces (fractions sum to 1);
   * a linear curve S(E)/N = a E/N gives DOS steps b = 4a on every level; a decreasing curve
-    is rejected;
+    or a non-finite value is rejected; where a curve turns down its steps are flat;
   * with the exact DOS of an L = 3 realization as the seed, the first sampling round is
     already flat over the whole range, so the seeded iteration converges at once while the
     plain start needs several rounds;
@@ -95,10 +95,20 @@ def test_seed_from_linear_curve_and_rejection(orc):
     k_s = orc.seed_from_grid(N, eb, k_top, y, b)
     assert k_s == (-2 * N - eb + 3) // 4
     assert np.allclose(b[k_s:k_top - 1], 4 * a, atol=N * 2e-6)   # float32 curve: N x (a few ulp)
-    assert (b[:k_s] == 0).all()
+    assert (b[:k_s] == 0).all() and (b[k_top:] == 0).all()
     b2 = np.zeros_like(b)
-    assert orc.seed_from_grid(N, eb, k_top, -y, b2) == -1
+    assert orc.seed_from_grid(N, eb, k_top, -y, b2) == -1            # decreasing: no information
     assert not b2.any()
+    y_nan = y.copy()
+    y_nan[100] = np.nan
+    assert orc.seed_from_grid(N, eb, k_top, y_nan, b2) == -1
+    # increasing above e = -1.5, decreasing below: flat steps below the turn
+    y3 = np.where(e >= -1.5, a * e, a * (-3.0 - e)).astype(np.float32)
+    b3 = np.zeros_like(b)
+    assert orc.seed_from_grid(N, eb, k_top, y3, b3) == k_s
+    E = eb + 4 * np.arange(len(b3))
+    assert (b3[(E >= -1.5 * N + 8) & (E < 4 * k_top + eb)] > 0).all()
+    assert not b3[(E < -1.5 * N - 8)].any()
 
 
 def test_seeded_iteration_with_exact_dos_converges_at_once(orc):
