@@ -65,6 +65,32 @@ def setup(nfm, mix, W, profile):
     return b, Ls
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweeps_L6_c2_traffic.txt")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2011_08560_amd", "csrc", "sweep.hip")
+
+
+def measured_traffic(config, sweeps_per_launch):
+    """HBM bytes per launch of the sweep kernel from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, each scaled by the same counter's reading for a copy of known size), or None
+    when there is none for this workload or the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+        digest = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != digest or kv.get("config") != config:
+            return None
+        if int(kv.get("sweeps_per_launch", -1)) != sweeps_per_launch:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _oracle_iteration(args):
     L, rid, W, sweeps, profile = args
     from oracle import oracle as orc
@@ -105,6 +131,9 @@ def main():
     ap.add_argument("--speculate", type=int, default=-1, choices=[-1, 0, 1],
                     help="speculative table lookups: -1 automatic, 0 off, 1 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a reference dispatch of known traffic "
+                         "for hardware-counter calibration); outside the timed region")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported here "
@@ -113,6 +142,13 @@ def main():
 
     import torch
     from paper_2011_08560_amd import nfm
+
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     mix, W, S, desc = CONFIGS[args.config]
     S = args.sweeps or S
@@ -127,8 +163,9 @@ def main():
         b.run_sweeps(64)                  # one short round so that the tables have their working shape
         b.rec_update(0.5)
         tuned, _ = b.autotune(calib_sweeps=256)
-    elif args.speculate != -1:
-        b.set_tuning(speculate=args.speculate)
+    else:
+        # 1000 sweeps per launch: the rounds of 1e4 / 1e5 sweeps split into equal launches
+        b.set_tuning(speculate=args.speculate, sweeps_per_launch=min(1000, S))
     stream = torch.cuda.current_stream()
     attempts_per_step = W * S * sum(l ** 3 for l in Ls)
     tn = b.get_tuning()
@@ -191,7 +228,9 @@ def main():
                                                "alpha": profile[2]}},
         "round_trips_per_s": trips / wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(args.config, tn["sweeps_per_launch"]) if S % tn["sweeps_per_launch"] == 0
+                     else None,
                      "kernel": kernel, "avg_launch_ms": avg_launch_s * 1e3,
                      "alg_ops_per_attempt": ALG_OPS_PER_ATTEMPT, "speculate": args.speculate},
     }

@@ -156,6 +156,15 @@ def generate(Ls, n_per_L, n_sweeps, f_tol, n_max, chunk=4096, first_id=0, log=No
     return torch.cat(xs), torch.cat(ys), torch.cat(ms), stats
 
 
+def infer(mlp, x):
+    """BF16 inference over any number of realizations, in chunks of the network's batch size."""
+    import torch
+    out = torch.empty((x.shape[0], nfm.Mlp.N_OUT), dtype=torch.float32, device=x.device)
+    for s in range(0, x.shape[0], mlp.batch_max):
+        mlp.infer_bf16(x[s:s + mlp.batch_max].contiguous(), out=out[s:s + mlp.batch_max])
+    return out
+
+
 def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID):
     """Paired comparison on fresh realizations: the same seeds, the same canonical run, then the
     plain start against the seeded one. Returns the rounds to converge of both arms."""
@@ -164,7 +173,7 @@ def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID):
     canonical_features(plain)
     x = canonical_features(seeded)
     mlp.to_bf16()
-    curves = mlp.infer_bf16(x)
+    curves = infer(mlp, x)
     seeded.rec_init(0, 1.0, 0.0)
     k_seed = seeded.rec_seed_grid(curves)
     it_plain = iterate(plain, n_sweeps, f_tol, n_max)

@@ -202,3 +202,21 @@ def test_adam_first_step_and_gelu_value():
     t0 = theta.copy()
     mlp.adam_step(theta, g, m, v, 1, 1e-3)
     assert np.allclose(theta - t0, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+
+
+def test_rec_targets_linear_estimate(orc):
+    """S linear in E (S = c (E - E_top)) gives y = c (e N - E_top)/N on the defined grid points,
+    masked below E(k_lo)."""
+    N, eb = 216, -648
+    K = 3 * N // 2 + 1
+    k_lo, k_top = 60, 162
+    c = 0.35
+    E = eb + 4 * np.arange(K)
+    S = np.zeros(K)
+    S[k_lo:k_top + 1] = c * (E[k_lo:k_top + 1] - E[k_top])
+    y, m = orc.rec_targets(N, eb, k_lo, k_top, S)
+    e = -2.0 + 2.0 * np.arange(256) / 255.0
+    inside = e * N >= eb + 4 * k_lo
+    assert np.array_equal(m, inside.astype(float))
+    assert np.allclose(y[inside], c * (e[inside] * N - E[k_top]) / N, atol=1e-12)
+    assert not y[~inside].any()
