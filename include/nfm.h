@@ -247,7 +247,8 @@ nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const dou
  *     resolves, which shortens a walker's serial chain at the cost of a second table read. The
  *     plain form overlaps its single table read with generator work instead, which measures
  *     faster on gfx950 at every occupancy tried.
- *   sweeps_per_launch: sweeps per kernel launch (0 = 1024).
+ *   sweeps_per_launch: sweeps per kernel launch, at most 2^20 (0 = 1024). A launch keeps its
+ *     walkers' histogram counts on chip and adds them to the histograms when it ends.
  *   schedule: 0 = one launch per lattice size of the batch; 1 = one persistent launch for the
  *     whole batch, whose workgroups take waves of walkers from a queue ordered by decreasing N
  *     (longest first), so that realizations of uneven size share the GPU.

@@ -803,10 +803,11 @@ nfm_status nfm_rec_set_state(nfm_ctx* c, int32_t r, const double* b, const doubl
 
 nfm_status nfm_set_tuning(nfm_ctx* c, const nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
-  if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0 || t->schedule < 0 || t->schedule > 1 ||
+  if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0 || t->sweeps_per_launch > (1 << 20) ||
+      t->schedule < 0 || t->schedule > 1 ||
       t->waves_per_cu < 0 || t->waves_per_cu > 64)
     return fail(c, NFM_EINVAL,
-                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch >= 0, schedule in {0,1}, waves_per_cu in [0,64]");
+                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch in [0, 2^20], schedule in {0,1}, waves_per_cu in [0,64]");
   c->speculate = t->speculate;
   c->sweeps_per_launch = t->sweeps_per_launch == 0 ? kMaxSweepsPerLaunch : (uint32_t)t->sweeps_per_launch;
   c->schedule = t->schedule;

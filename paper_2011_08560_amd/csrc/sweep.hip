@@ -66,6 +66,8 @@ __device__ __forceinline__ void unpack(typename Geo<L>::PW v, uint32_t* w) {
   for (int i = 0; i < G::NWP; ++i) w[i] = (uint32_t)(v >> (32 * i));
 }
 
+constexpr int kHistAbove = 64;  // histogram levels kept on chip above the table rows
+
 __device__ __forceinline__ int floor_div4(int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); }
 __device__ __forceinline__ int ceil_div4(int a) { return -floor_div4(-a); }
 
@@ -234,9 +236,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   //   [0, rows*32)        threshold table, each row permuted from u-order to m-order: entry j
   //                       holds the threshold of the step m = j (j < 4) or m = j - 8 (j > 4);
   //   tempering only      energies by slot, exchange decisions, exchange counters (3 x 256 B);
-  //   then                the realization's couplings in the kernel layout.
+  //   then                the realization's couplings in the kernel layout;
+  //   multicanonical only the launch's histogram over the table rows and kHistAbove levels above
+  //   them (W is constant above the top, where walkers spend a fair share of their time).
   const uint32_t sE = (uint32_t)rows * 32u, sD = sE + 256u, sAcc = sD + 256u;
   const uint32_t jbase = PT ? sAcc + 256u : sE;
+  const uint32_t hbase = jbase + 4u * (uint32_t)jk_words(L);
   {
     const uint32_t* gt = PT ? A.pt_metro : A.tables + RI.table_off;
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
@@ -247,7 +252,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     const uint32_t* jg = A.jk + RI.jk_off;
     for (int e = threadIdx.x; e < jk_words(L); e += 64) lds_store_i32(jbase + 4u * (uint32_t)e, (int)jg[e]);
   }
-  if constexpr (PT) lds_store_i32(sAcc + 4u * threadIdx.x, 0);
+  if constexpr (PT) {
+    lds_store_i32(sAcc + 4u * threadIdx.x, 0);
+  } else {
+    for (int e = threadIdx.x; e < rows + kHistAbove; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
+  }
   __syncthreads();
 
   // walker state -> registers. One array per (colour, word) so that each stays small
@@ -560,9 +569,16 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       R = B;
       __syncthreads();
     } else {
-      // end of sweep: histogram and trace
-      const int k = (B >> 5) + row0;
-      if (k >= 0 && k < RI.K) atomicAdd(A.hist + RI.level_off + k, 1ULL);  // always true for exact energies
+      // end of sweep: histogram (rows of the table in LDS, the rare levels outside them directly)
+      // and trace
+      const int kr = B >> 5;
+      const int k = kr + row0;
+      if (kr >= 0 && kr < rows + kHistAbove && k < RI.K) {
+        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(uintptr_t)(hbase + 4u * (uint32_t)kr), 1u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else if (k >= 0 && k < RI.K) {  // always true for exact energies
+        atomicAdd(A.hist + RI.level_off + k, 1ULL);
+      }
       if (t - A.trace_t0 < (uint64_t)A.trace_cap)
         A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
     }
@@ -592,6 +608,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     const int cidx = (int)(threadIdx.x & (uint32_t)(M - 1));
     if (cidx < M - 1) A.pt_acc[(gw / M) * (M - 1) + cidx] += (uint64_t)lds_load_i32(sAcc + 4u * threadIdx.x);
   } else {
+    // the launch's histogram counts (at most 64 walkers x 2^16 sweeps per row)
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows + kHistAbove; e += 64) {
+      const uint32_t c = (uint32_t)lds_load_i32(hbase + 4u * (uint32_t)e);
+      if (c) atomicAdd(A.hist + RI.level_off + row0 + e, (unsigned long long)c);
+    }
     A.ws.E[gw] = e_base + 4 * ((B >> 5) + row0);
     A.ws.E_min[gw] = e_base + 4 * ((tr.Bmin >> 5) + row0);
     A.ws.rt_state[gw] = tr.state;
@@ -662,7 +684,7 @@ template <int L>
 static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, bool spec, bool pt, hipStream_t s) {
   const size_t jb = (size_t)jk_words(L) * 4;
   if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
-  const size_t lds = (size_t)lds_rows * 8 * sizeof(uint32_t) + jb;
+  const size_t lds = (size_t)lds_rows * 9 * sizeof(uint32_t) + jb + 4 * kHistAbove;   // table, couplings, histogram
   return spec ? launch_LS<L, true, false>(a, n_waves, lds, s) : launch_LS<L, false, false>(a, n_waves, lds, s);
 }
 
@@ -698,7 +720,7 @@ static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4, s,
+  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), (size_t)lds_rows * 36 + (size_t)jk_words(kMaxL) * 4 + 4 * kHistAbove, s,
                      a, order, n_items, counter);
   return hipGetLastError();
 }
@@ -707,7 +729,7 @@ int queue_blocks_per_cu(bool spec, int lds_rows) {
   int n = 0;
   const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
                        : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, (size_t)lds_rows * 36 + (size_t)jk_words(kMaxL) * 4 + 4 * kHistAbove) !=
       hipSuccess)
     return 0;
   return n;
