@@ -564,8 +564,11 @@ static nfm::SweepArgs muca_args(nfm_ctx* c, uint64_t t0, uint32_t n, int trace_c
 // Launch n multicanonical sweeps starting at sweep t0 under the given tuning (no checks).
 static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int speculate, uint32_t per_launch,
                                 int schedule, int waves_per_cu, int trace_cap) {
-  int lds_all = 1;
-  for (const auto& ri : c->reals) lds_all = std::max(lds_all, ri.rows);
+  int lds_all = 1, k_all = 1;
+  for (const auto& ri : c->reals) {
+    lds_all = std::max(lds_all, ri.rows);
+    k_all = std::max(k_all, ri.K);
+  }
   uint64_t done = 0;
   while (done < n_sweeps) {
     const uint32_t chunk = (uint32_t)std::min<uint64_t>(per_launch, n_sweeps - done);
@@ -573,23 +576,27 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
     if (schedule == 1) {
       const bool spec = speculate == 1;
       int wpc = waves_per_cu;
-      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all));
+      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all, k_all));
       const int64_t grid = std::min<int64_t>(c->lay.total_waves, (int64_t)wpc * c->n_cu);
       hipError_t e = nfm::launch_muca_queue(a, (const int32_t*)(c->ws + c->lay.order), (int)c->lay.total_waves,
-                                            (uint32_t*)(c->ws + c->lay.counter), (int)grid, lds_all, spec, c->stream);
+                                            (uint32_t*)(c->ws + c->lay.counter), (int)grid, lds_all, k_all, spec, c->stream);
       if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_queue: ") + hipGetErrorString(e));
     } else {
       for (size_t g = 0; g < c->group_L.size(); ++g) {
         const int L = c->group_L[g];
-        int lds_rows = 1;
+        int lds_rows = 1, hist_levels = 1;
         for (const auto& ri : c->reals)
-          if (ri.L == L) lds_rows = std::max(lds_rows, ri.rows);
+          if (ri.L == L) {
+            lds_rows = std::max(lds_rows, ri.rows);
+            hist_levels = std::max(hist_levels, ri.K);
+          }
         a.wave_real = c->d_waves() + c->group_first_wave[g];
         a.wave_wl = c->d_waves() + c->lay.total_waves + c->group_first_wave[g];
         // Speculation is off unless asked for: the table read of the plain form is already
         // overlapped with generator work, which costs fewer instructions than a second read.
         const bool spec = speculate == 1;
-        hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, spec, c->stream);
+        hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, hist_levels, spec,
+                                                     c->stream);
         if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
       }
     }

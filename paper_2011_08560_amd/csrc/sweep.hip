@@ -66,7 +66,6 @@ __device__ __forceinline__ void unpack(typename Geo<L>::PW v, uint32_t* w) {
   for (int i = 0; i < G::NWP; ++i) w[i] = (uint32_t)(v >> (32 * i));
 }
 
-constexpr int kHistAbove = 64;  // histogram levels kept on chip above the table rows
 
 __device__ __forceinline__ int floor_div4(int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); }
 __device__ __forceinline__ int ceil_div4(int a) { return -floor_div4(-a); }
@@ -227,7 +226,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   const int wl = A.wave_wl[wave] + (int)threadIdx.x;
   const RealInfo& RI = A.reals[r];
   const int row0 = PT ? 0 : RI.row0, rows = PT ? A.pt_M : RI.rows;
-  const int e_base = RI.e_base, walkers = RI.walkers;
+  const int e_base = RI.e_base, walkers = RI.walkers, K = RI.K;
   const int e_bot = RI.e_bot, e_top = RI.e_top;
   const uint32_t real_id = RI.real_id;
   const int64_t gw = RI.walker_off + wl;
@@ -237,8 +236,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   //                       holds the threshold of the step m = j (j < 4) or m = j - 8 (j > 4);
   //   tempering only      energies by slot, exchange decisions, exchange counters (3 x 256 B);
   //   then                the realization's couplings in the kernel layout;
-  //   multicanonical only the launch's histogram over the table rows and kHistAbove levels above
-  //   them (W is constant above the top, where walkers spend a fair share of their time).
+  //   multicanonical only the launch's histogram over all K levels of the realization (walkers
+  //   leave the table rows in both directions: above the top, where W is constant, and below the
+  //   lowest known level in the first rounds), flushed to HBM once at the end.
   const uint32_t sE = (uint32_t)rows * 32u, sD = sE + 256u, sAcc = sD + 256u;
   const uint32_t jbase = PT ? sAcc + 256u : sE;
   const uint32_t hbase = jbase + 4u * (uint32_t)jk_words(L);
@@ -255,7 +255,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   if constexpr (PT) {
     lds_store_i32(sAcc + 4u * threadIdx.x, 0);
   } else {
-    for (int e = threadIdx.x; e < rows + kHistAbove; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
+    for (int e = threadIdx.x; e < K; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
   }
   __syncthreads();
 
@@ -569,16 +569,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       R = B;
       __syncthreads();
     } else {
-      // end of sweep: histogram (rows of the table in LDS, the rare levels outside them directly)
-      // and trace
-      const int kr = B >> 5;
-      const int k = kr + row0;
-      if (kr >= 0 && kr < rows + kHistAbove && k < RI.K) {
-        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(uintptr_t)(hbase + 4u * (uint32_t)kr), 1u,
+      // end of sweep: histogram (on chip) and trace
+      const int k = (B >> 5) + row0;
+      if ((uint32_t)k < (uint32_t)K)  // always true for exact energies
+        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(uintptr_t)(hbase + 4u * (uint32_t)k), 1u,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      } else if (k >= 0 && k < RI.K) {  // always true for exact energies
-        atomicAdd(A.hist + RI.level_off + k, 1ULL);
-      }
       if (t - A.trace_t0 < (uint64_t)A.trace_cap)
         A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
     }
@@ -608,11 +603,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     const int cidx = (int)(threadIdx.x & (uint32_t)(M - 1));
     if (cidx < M - 1) A.pt_acc[(gw / M) * (M - 1) + cidx] += (uint64_t)lds_load_i32(sAcc + 4u * threadIdx.x);
   } else {
-    // the launch's histogram counts (at most 64 walkers x 2^16 sweeps per row)
+    // the launch's histogram counts (at most 64 walkers x 2^20 sweeps per level)
     __syncthreads();
-    for (int e = threadIdx.x; e < rows + kHistAbove; e += 64) {
+    for (int e = threadIdx.x; e < K; e += 64) {
       const uint32_t c = (uint32_t)lds_load_i32(hbase + 4u * (uint32_t)e);
-      if (c) atomicAdd(A.hist + RI.level_off + row0 + e, (unsigned long long)c);
+      if (c) atomicAdd(A.hist + RI.level_off + e, (unsigned long long)c);
     }
     A.ws.E[gw] = e_base + 4 * ((B >> 5) + row0);
     A.ws.E_min[gw] = e_base + 4 * ((tr.Bmin >> 5) + row0);
@@ -681,34 +676,37 @@ static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, h
 }
 
 template <int L>
-static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, bool spec, bool pt, hipStream_t s) {
+static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec, bool pt,
+                           hipStream_t s) {
   const size_t jb = (size_t)jk_words(L) * 4;
   if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
-  const size_t lds = (size_t)lds_rows * 9 * sizeof(uint32_t) + jb + 4 * kHistAbove;   // table, couplings, histogram
+  const size_t lds = (size_t)lds_rows * 32 + jb + (size_t)hist_levels * 4;   // table, couplings, histogram
   return spec ? launch_LS<L, true, false>(a, n_waves, lds, s) : launch_LS<L, false, false>(a, n_waves, lds, s);
 }
 
-static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, bool pt, hipStream_t s) {
+static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec, bool pt,
+                             hipStream_t s) {
   switch (L) {
-    case 2: return launch_L<2>(a, n_waves, lds_rows, spec, pt, s);
-    case 4: return launch_L<4>(a, n_waves, lds_rows, spec, pt, s);
-    case 6: return launch_L<6>(a, n_waves, lds_rows, spec, pt, s);
-    case 8: return launch_L<8>(a, n_waves, lds_rows, spec, pt, s);
-    case 10: return launch_L<10>(a, n_waves, lds_rows, spec, pt, s);
-    case 12: return launch_L<12>(a, n_waves, lds_rows, spec, pt, s);
+    case 2: return launch_L<2>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
+    case 4: return launch_L<4>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
+    case 6: return launch_L<6>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
+    case 8: return launch_L<8>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
+    case 10: return launch_L<10>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
+    case 12: return launch_L<12>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
 
-hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, bool spec, hipStream_t s) {
-  return launch_any(L, a, n_waves, lds_rows, spec, false, s);
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec,
+                              hipStream_t s) {
+  return launch_any(L, a, n_waves, lds_rows, hist_levels, spec, false, s);
 }
 
 template <bool SPEC>
 static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
-                                 int lds_rows, hipStream_t s) {
+                                 size_t lds_bytes, hipStream_t s) {
   static int checked = 0;
   if (!checked) {
     hipFuncAttributes attr;
@@ -720,31 +718,36 @@ static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), (size_t)lds_rows * 36 + (size_t)jk_words(kMaxL) * 4 + 4 * kHistAbove, s,
-                     a, order, n_items, counter);
+  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), lds_bytes, s, a, order, n_items, counter);
   return hipGetLastError();
 }
 
-int queue_blocks_per_cu(bool spec, int lds_rows) {
+// LDS of the persistent kernel: the largest table, the couplings of the largest lattice and the
+// largest histogram of the batch.
+static size_t queue_lds_bytes(int lds_rows, int hist_levels) {
+  return (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4 + (size_t)hist_levels * 4;
+}
+
+int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels) {
   int n = 0;
   const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
                        : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, (size_t)lds_rows * 36 + (size_t)jk_words(kMaxL) * 4 + 4 * kHistAbove) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, queue_lds_bytes(lds_rows, hist_levels)) != hipSuccess)
     return 0;
   return n;
 }
 
 hipError_t launch_muca_queue(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
-                             int lds_rows, bool spec, hipStream_t s) {
+                             int lds_rows, int hist_levels, bool spec, hipStream_t s) {
   if (grid < 1 || n_items < 0) return hipErrorInvalidValue;
-  return spec ? launch_queue_S<true>(a, order, n_items, counter, grid, lds_rows, s)
-              : launch_queue_S<false>(a, order, n_items, counter, grid, lds_rows, s);
+  const size_t lds = queue_lds_bytes(lds_rows, hist_levels);
+  return spec ? launch_queue_S<true>(a, order, n_items, counter, grid, lds, s)
+              : launch_queue_S<false>(a, order, n_items, counter, grid, lds, s);
 }
 
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s) {
   if (a.pt_M < 2 || a.pt_M > kMaxReplicas || (a.pt_M & (a.pt_M - 1)) != 0 || a.pt_D < 1) return hipErrorInvalidValue;
-  return launch_any(L, a, n_waves, 1, false, true, s);
+  return launch_any(L, a, n_waves, 1, 0, false, true, s);
 }
 
 }  // namespace nfm
