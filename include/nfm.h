@@ -253,12 +253,18 @@ nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const dou
  *     whole batch, whose workgroups take waves of walkers from a queue ordered by decreasing N
  *     (longest first), so that realizations of uneven size share the GPU.
  *   waves_per_cu: persistent schedule only, resident workgroups per compute unit (0 = as many
- *     as fit). */
+ *     as fit).
+ *   hist: extent of a launch's on-chip histogram. 0 automatic: every level of the realization
+ *     when that leaves as many workgroups resident per compute unit as the window (capped at the
+ *     ones the launch needs), else the window; 1 window: the table's rows and 64 levels on either
+ *     side, levels outside it counted in device memory directly; 2 every level; 3 the table's
+ *     rows alone (the most direct counting; for tests of that path). */
 typedef struct {
   int32_t speculate;
   int32_t sweeps_per_launch;
   int32_t schedule;
   int32_t waves_per_cu;
+  int32_t hist;
 } nfm_tuning;
 nfm_status nfm_set_tuning(nfm_ctx* ctx, const nfm_tuning* tuning);
 nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);

@@ -127,6 +127,7 @@ struct nfm_ctx {
   uint64_t sweeps = 0, trace_t0 = 0;
   bool couplings = false;
   int speculate = -1;                      // -1 auto, 0 off, 1 on
+  int hist_mode = 0;                       // on-chip histogram: 0 auto, 1 window, 2 every level, 3 rows
   uint32_t sweeps_per_launch = kMaxSweepsPerLaunch;
   int schedule = 0;                        // 0: one launch per lattice size, 1: persistent work queue
   int waves_per_cu = 0;                    // persistent grid: workgroups per CU (0 = as many as fit)
@@ -563,7 +564,7 @@ static nfm::SweepArgs muca_args(nfm_ctx* c, uint64_t t0, uint32_t n, int trace_c
 
 // Launch n multicanonical sweeps starting at sweep t0 under the given tuning (no checks).
 static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int speculate, uint32_t per_launch,
-                                int schedule, int waves_per_cu, int trace_cap) {
+                                int schedule, int waves_per_cu, int hist_mode, int trace_cap) {
   int lds_all = 1, k_all = 1;
   for (const auto& ri : c->reals) {
     lds_all = std::max(lds_all, ri.rows);
@@ -576,10 +577,11 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
     if (schedule == 1) {
       const bool spec = speculate == 1;
       int wpc = waves_per_cu;
-      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all, k_all));
+      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all, k_all, hist_mode));
       const int64_t grid = std::min<int64_t>(c->lay.total_waves, (int64_t)wpc * c->n_cu);
       hipError_t e = nfm::launch_muca_queue(a, (const int32_t*)(c->ws + c->lay.order), (int)c->lay.total_waves,
-                                            (uint32_t*)(c->ws + c->lay.counter), (int)grid, lds_all, k_all, spec, c->stream);
+                                            (uint32_t*)(c->ws + c->lay.counter), (int)grid, c->n_cu, lds_all, k_all,
+                                            hist_mode, spec, c->stream);
       if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_queue: ") + hipGetErrorString(e));
     } else {
       for (size_t g = 0; g < c->group_L.size(); ++g) {
@@ -595,8 +597,8 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
         // Speculation is off unless asked for: the table read of the plain form is already
         // overlapped with generator work, which costs fewer instructions than a second read.
         const bool spec = speculate == 1;
-        hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, hist_levels, spec,
-                                                     c->stream);
+        hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, hist_levels, c->n_cu,
+                                                     hist_mode, spec, c->stream);
         if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
       }
     }
@@ -613,7 +615,7 @@ nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
   if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
     return fail(c, NFM_ERANGE, "run_sweeps: the sweep counter must stay below 2^32");
   nfm_status st = muca_launches(c, c->sweeps, n_sweeps, c->speculate, c->sweeps_per_launch, c->schedule,
-                                c->waves_per_cu, c->trace_cap);
+                                c->waves_per_cu, c->hist_mode, c->trace_cap);
   if (st != NFM_OK) return st;
   c->sweeps += n_sweeps;
   return NFM_OK;
@@ -812,13 +814,15 @@ nfm_status nfm_set_tuning(nfm_ctx* c, const nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
   if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0 || t->sweeps_per_launch > (1 << 20) ||
       t->schedule < 0 || t->schedule > 1 ||
-      t->waves_per_cu < 0 || t->waves_per_cu > 64)
+      t->waves_per_cu < 0 || t->waves_per_cu > 64 || t->hist < 0 || t->hist > 3)
     return fail(c, NFM_EINVAL,
-                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch in [0, 2^20], schedule in {0,1}, waves_per_cu in [0,64]");
+                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch in [0, 2^20], schedule in {0,1}, waves_per_cu in "
+                "[0,64], hist in {0,1,2,3}");
   c->speculate = t->speculate;
   c->sweeps_per_launch = t->sweeps_per_launch == 0 ? kMaxSweepsPerLaunch : (uint32_t)t->sweeps_per_launch;
   c->schedule = t->schedule;
   c->waves_per_cu = t->waves_per_cu;
+  c->hist_mode = t->hist;
   return NFM_OK;
 }
 
@@ -828,6 +832,7 @@ nfm_status nfm_get_tuning(const nfm_ctx* c, nfm_tuning* t) {
   t->sweeps_per_launch = (int32_t)c->sweeps_per_launch;
   t->schedule = c->schedule;
   t->waves_per_cu = c->waves_per_cu;
+  t->hist = c->hist_mode;
   return NFM_OK;
 }
 
@@ -875,7 +880,7 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
         std::istringstream is(line);
         std::string k;
         nfm_tuning t{};
-        if ((is >> k >> t.speculate >> t.sweeps_per_launch >> t.schedule >> t.waves_per_cu) && k == key) {
+        if ((is >> k >> t.speculate >> t.sweeps_per_launch >> t.schedule >> t.waves_per_cu >> t.hist) && k == key) {
           hit = t;
           found = 1;
         }
@@ -898,10 +903,10 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     const int chunks[] = {64, 256, 1024};
     for (int spec = 0; spec <= 1; ++spec)
       for (int ch : chunks) {
-        cand.push_back(nfm_tuning{spec, ch, 0, 0});
-        cand.push_back(nfm_tuning{spec, ch, 1, 0});
+        cand.push_back(nfm_tuning{spec, ch, 0, 0, 0});
+        cand.push_back(nfm_tuning{spec, ch, 1, 0, 0});
         for (int wpc : {4, 8})
-          if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc});
+          if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc, 0});
       }
     hipEvent_t e0, e1;
     NFM_HIP(c, hipEventCreate(&e0));
@@ -917,12 +922,12 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     int nres = 0;
     nfm_status st = NFM_OK;
     // one untimed warm-up pass so that first-launch costs do not favour later candidates
-    st = muca_launches(c, c->sweeps, (uint64_t)std::min(calib_sweeps, 64), 0, kMaxSweepsPerLaunch, 0, 0, 0);
+    st = muca_launches(c, c->sweeps, (uint64_t)std::min(calib_sweeps, 64), 0, kMaxSweepsPerLaunch, 0, 0, 0, 0);
     for (size_t i = 0; i < cand.size() && st == NFM_OK; ++i) {
       const nfm_tuning& t = cand[i];
       if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, NFM_EDEVICE, "autotune: event"); break; }
       st = muca_launches(c, c->sweeps, (uint64_t)calib_sweeps, t.speculate, (uint32_t)t.sweeps_per_launch, t.schedule,
-                         t.waves_per_cu, 0);
+                         t.waves_per_cu, t.hist, 0);
       if (st != NFM_OK) break;
       float ms = 0.f;
       if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -950,7 +955,7 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     if (cache_path) {
       std::ofstream f(cache_path, std::ios::app);
       if (f) f << key << " " << bt.speculate << " " << bt.sweeps_per_launch << " " << bt.schedule << " " << bt.waves_per_cu
-               << "\n";
+               << " " << bt.hist << "\n";
     }
     if (best) *best = bt;
     return nfm_set_tuning(c, &bt);

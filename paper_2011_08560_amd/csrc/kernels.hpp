@@ -63,12 +63,15 @@ hipError_t launch_features(const RealInfo* reals, int n_real, const uint32_t* ja
 
 // sweep.hip
 // lds_rows / hist_levels: the most table rows / levels (K) of any realization in the launch
-hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec,
-                              hipStream_t s);
+// (n_cu: compute units of the device; hist_mode: on-chip histogram 0 auto, 1 window, 2 every level,
+// 3 the table rows alone)
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
+                              int hist_mode, bool spec, hipStream_t s);
 // persistent launch over all waves of the batch; order = wave indices, longest first
-hipError_t launch_muca_queue(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
-                             int lds_rows, int hist_levels, bool spec, hipStream_t s);
-int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels);  // resident workgroups per CU (0 on error)
+hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uint32_t* counter, int grid, int n_cu,
+                             int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s);
+// resident workgroups per CU of the persistent kernel (0 on error)
+int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode);
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s);
 bool sweep_supported(int L);
 

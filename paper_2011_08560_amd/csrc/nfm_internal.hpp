@@ -64,11 +64,13 @@ struct SweepArgs {
   unsigned long long* hist;
   int32_t* trace;
   int32_t trace_cap;
-  int32_t pad;
+  // on-chip histogram window of a realization: levels [max(0, row0 - hist_margin), + hist_n);
+  // counts outside it go to HBM directly
+  int32_t hist_margin;
   uint64_t trace_t0;         // first traced sweep
   uint64_t t0;               // first sweep of this launch
   uint32_t n_sweeps;
-  uint32_t pad2;
+  int32_t hist_n;
   uint64_t walker_seed;
   // parallel tempering (unused by the multicanonical kernel)
   const uint32_t* pt_metro;  // M x 8 Metropolis thresholds, u-order

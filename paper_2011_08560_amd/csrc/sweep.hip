@@ -12,6 +12,7 @@
 // block is fixed; it is computed for the whole block at once with word-parallel
 // bit operations (six flag strings and a bit-sliced adder). The attempts then run
 // one after the other, since each acceptance reads the walker's current energy.
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -236,12 +237,14 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   //                       holds the threshold of the step m = j (j < 4) or m = j - 8 (j > 4);
   //   tempering only      energies by slot, exchange decisions, exchange counters (3 x 256 B);
   //   then                the realization's couplings in the kernel layout;
-  //   multicanonical only the launch's histogram over all K levels of the realization (walkers
-  //   leave the table rows in both directions: above the top, where W is constant, and below the
-  //   lowest known level in the first rounds), flushed to HBM once at the end.
+  //   multicanonical only the launch's histogram over a window of levels around the table rows
+  //   (all K levels where that costs no occupancy: walkers leave the rows in both directions,
+  //   above the top where W is constant and below the lowest known level in the first rounds),
+  //   flushed to HBM once at the end; levels outside the window are counted in HBM directly.
   const uint32_t sE = (uint32_t)rows * 32u, sD = sE + 256u, sAcc = sD + 256u;
   const uint32_t jbase = PT ? sAcc + 256u : sE;
   const uint32_t hbase = jbase + 4u * (uint32_t)jk_words(L);
+  const int hlo = max(0, row0 - A.hist_margin), hn = A.hist_n;
   {
     const uint32_t* gt = PT ? A.pt_metro : A.tables + RI.table_off;
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
@@ -255,7 +258,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   if constexpr (PT) {
     lds_store_i32(sAcc + 4u * threadIdx.x, 0);
   } else {
-    for (int e = threadIdx.x; e < K; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
+    for (int e = threadIdx.x; e < hn; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
   }
   __syncthreads();
 
@@ -316,118 +319,141 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   PhiloxKeysV kv = philox_round_keys_v(key0, key1);
   const uint32_t ctr3 = ((uint32_t)wl << 8) | (PT ? kTagPT : kTagAcc);
 
+  // Level steps of the sites of block (c, z), a plane-colour string, from the other colour's
+  // spins and the couplings: V[g8] holds, byte-interleaved, the three bits of m = 3 - u of eight
+  // sites. The other colour does not change while colour c is updated, so the block after the
+  // current one is prepared while the current one runs.
+  auto block_steps = [&](int c, int z, uint32_t (&V)[NB]) __attribute__((always_inline)) {
+    const int zp = (z + 1 == L) ? 0 : z + 1;
+    const int zm = (z == 0) ? L - 1 : z - 1;
+    uint32_t Cw[NWP], Ow[NWP], Pw[NWP], Mw[NWP];
+#pragma unroll
+    for (int w = 0; w < NWP; ++w) {
+      Cw[w] = lat(c, w)[z];
+      Ow[w] = lat(1 - c, w)[z];
+      Pw[w] = lat(1 - c, w)[zp];
+      Mw[w] = lat(1 - c, w)[zm];
+    }
+    const uint32_t jz = jbase + 4u * (uint32_t)((c * L + z) * 6 * NWP);
+    uint32_t Jw[6][NWP];
+    {
+      // 6 NWP words, 8-byte aligned: read as pairs, all issued before the first use
+      uint64_t jv[3 * NWP];
+#pragma unroll
+      for (int k = 0; k < 3 * NWP; ++k)
+        jv[k] = *(const __attribute__((address_space(3))) uint64_t*)(uintptr_t)(jz + 8u * (uint32_t)k);
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int w = 0; w < NWP; ++w) {
+          const int e = k * NWP + w;
+          Jw[k][w] = (uint32_t)(jv[e >> 1] >> (32 * (e & 1)));
+        }
+    }
+    // flags: bit set <=> bond unsatisfied (S_i xor S_j xor [J = -1])
+    const PW own = pack<L>(Cw), O = pack<L>(Ow), Zp = pack<L>(Pw), Zm = pack<L>(Mw);
+    constexpr PW ALL = G::all_bits();
+    const PW Yp = ((O >> G::F) | (O << (G::F * (L - 1)))) & ALL;
+    const PW Ym = ((O << G::F) | (O >> (G::F * (L - 1)))) & ALL;
+    const PW Xm1 = ((O << 1) & G::fields(1, G::H - 1)) | ((O >> (G::H - 1)) & G::fields(0, 1));
+    const PW Xp1 = ((O >> 1) & G::fields(0, G::H - 1)) | ((O << (G::H - 1)) & G::fields(G::H - 1, 1));
+    // rows whose sites have odd x (phi = 1) take their "other" x-neighbour at j+1
+    const PW PHI = ((c + z) & 1) ? G::rows_of_parity(0) : G::rows_of_parity(1);
+    const PW Xo = (Xp1 & PHI) | (Xm1 & ~PHI);
+    const PW f1 = own ^ Zp ^ pack<L>(Jw[0]);
+    const PW f2 = own ^ Zm ^ pack<L>(Jw[1]);
+    const PW f3 = own ^ Yp ^ pack<L>(Jw[2]);
+    const PW f4 = own ^ Ym ^ pack<L>(Jw[3]);
+    const PW f5 = own ^ O ^ pack<L>(Jw[4]);
+    const PW f6 = own ^ Xo ^ pack<L>(Jw[5]);
+    // Bit-sliced u = f1 + ... + f6, delivered as the level step m = 3 - u in 3-bit two's
+    // complement: m = (7 - u) ^ 4, i.e. bits (~u0, ~u1, u2).
+    const PW s1 = f1 ^ f2 ^ f3, k1 = (f1 & f2) | (f3 & (f1 ^ f2));
+    const PW s2 = f4 ^ f5 ^ f6, k2 = (f4 & f5) | (f6 & (f4 ^ f5));
+    const PW t0 = s1 & s2;
+    uint32_t m0[NWP], m1[NWP], m2[NWP];
+    unpack<L>(~(s1 ^ s2), m0);
+    unpack<L>(~(k1 ^ k2 ^ t0), m1);
+    unpack<L>((k1 & k2) | (t0 & (k1 ^ k2)), m2);
+    // Byte-interleave: V[g8] = (0, m0.byte, m1.byte, m2.byte). For the site at bit b of
+    // that byte, (V & (0x01010100 << b)) * (2^(26-b) + 2^(19-b) + 2^(12-b)) puts its three
+    // bits at 2^34, 2^35, 2^36 and every other partial product at another single bit
+    // (no carries), so bits 2..4 of the high word are m & 7.
+#pragma unroll
+    for (int g8 = 0; g8 < NB; ++g8) {
+      const int w = g8 >> 2;
+      const uint32_t bsel = (uint32_t)(g8 & 3);
+      // perm selector bytes: 0x0c -> 0x00; 0..3 pick src1 bytes, 4..7 pick src0 bytes
+      const uint32_t lo = __builtin_amdgcn_perm(m1[w], m0[w], 0x0c00000cu | (bsel << 8) | ((4u + bsel) << 16));
+      V[g8] = __builtin_amdgcn_perm(m2[w], lo, 0x00020100u | ((4u + bsel) << 24));
+      asm volatile("" : "+v"(V[g8]));
+    }
+  };
+  // m & 7 of site q of a block in bits 2..4 (sign at bit 4) of a product high word
+  auto gather = [&](const uint32_t (&V)[NB], int q) __attribute__((always_inline)) -> uint32_t {
+    const int y = q / H, j = q % H;
+    const int p = y * FB + j, g8 = p >> 3, bb = p & 7;
+    // (2^26 + 2^19 + 2^12) >> bb: eight distinct constants in all
+    return __umulhi(V[g8] & (0x01010100u << bb), 0x04081000u >> bb);
+  };
+  auto lookup = [&](uint32_t hi, int Rv) __attribute__((always_inline)) -> uint32_t {
+    // Rv is a multiple of 32 in [0, Bmax]; (hi & 0x1c) is 4 (m & 7)
+    return *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)((hi & 0x1cu) | (uint32_t)Rv);
+  };
+  // Generator counter of group g (four sites) of block (c, z) in sweep t.
+  auto group_ctr = [&](int c, int z, int g, uint64_t t) __attribute__((always_inline)) -> PhiloxRun {
+    return PhiloxRun{((uint32_t)(c * L + z) << 8) | (uint32_t)g, (uint32_t)t, real_id, ctr3};
+  };
+  constexpr int NG = (Q + 3) / 4;
+  // The generator runs one group ahead: pr holds the words of the next group of four sites, and
+  // its rounds are spread over the attempts of the group before it (also across blocks, colours
+  // and sweeps), so that they fill the wait for each threshold read.
+  PhiloxRun pr = group_ctr(0, 0, 0, A.t0);
+  philox_rounds<0, 10>(pr, kv);
+
   for (uint32_t s = 0; s < A.n_sweeps; ++s) {
     const uint64_t t = A.t0 + s;
     const uint64_t tau0 = t * (uint64_t)N + 1u;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+      uint32_t Vc[NB];
+      block_steps(c, 0, Vc);
+      // the colour's first threshold; later ones are read by the attempt before (multicanonical)
+      // or one site ahead (tempering), across block ends
+      uint32_t hi_cur = gather(Vc, 0);
+      uint32_t th_fly = 0, addr_cur = 0;
+      if constexpr (!SPEC || PT) th_fly = lookup(hi_cur, R);
       // small lattices: planes unrolled (static register indices); larger ones: a plane loop
       // whose dynamic index selects registers of the per-(colour, word) arrays
 #pragma unroll kZUnroll
       for (int z = 0; z < L; ++z) {
-        const int zp = (z + 1 == L) ? 0 : z + 1;
-        const int zm = (z == 0) ? L - 1 : z - 1;
-        uint32_t Cw[NWP], Ow[NWP], Pw[NWP], Mw[NWP];
+        const bool has_next = z + 1 < L;
+        uint32_t Vn[NB];
+        if (has_next) block_steps(c, z + 1, Vn);
+        uint32_t Cw[NWP];
 #pragma unroll
-        for (int w = 0; w < NWP; ++w) {
-          Cw[w] = lat(c, w)[z];
-          Ow[w] = lat(1 - c, w)[z];
-          Pw[w] = lat(1 - c, w)[zp];
-          Mw[w] = lat(1 - c, w)[zm];
-        }
-        const uint32_t jz = jbase + 4u * (uint32_t)((c * L + z) * 6 * NWP);
-        uint32_t Jw[6][NWP];
-        {
-          // 6 NWP words, 8-byte aligned: read as pairs, all issued before the first use
-          uint64_t jv[3 * NWP];
-#pragma unroll
-          for (int k = 0; k < 3 * NWP; ++k)
-            jv[k] = *(const __attribute__((address_space(3))) uint64_t*)(uintptr_t)(jz + 8u * (uint32_t)k);
-#pragma unroll
-          for (int k = 0; k < 6; ++k)
-#pragma unroll
-            for (int w = 0; w < NWP; ++w) {
-              const int e = k * NWP + w;
-              Jw[k][w] = (uint32_t)(jv[e >> 1] >> (32 * (e & 1)));
-            }
-        }
-
-        // flags: bit set <=> bond unsatisfied (S_i xor S_j xor [J = -1])
-        const PW own = pack<L>(Cw), O = pack<L>(Ow), Zp = pack<L>(Pw), Zm = pack<L>(Mw);
-        constexpr PW ALL = G::all_bits();
-        const PW Yp = ((O >> G::F) | (O << (G::F * (L - 1)))) & ALL;
-        const PW Ym = ((O << G::F) | (O >> (G::F * (L - 1)))) & ALL;
-        const PW Xm1 = ((O << 1) & G::fields(1, G::H - 1)) | ((O >> (G::H - 1)) & G::fields(0, 1));
-        const PW Xp1 = ((O >> 1) & G::fields(0, G::H - 1)) | ((O << (G::H - 1)) & G::fields(G::H - 1, 1));
-        // rows whose sites have odd x (phi = 1) take their "other" x-neighbour at j+1
-        const PW PHI = ((c + z) & 1) ? G::rows_of_parity(0) : G::rows_of_parity(1);
-        const PW Xo = (Xp1 & PHI) | (Xm1 & ~PHI);
-        const PW f1 = own ^ Zp ^ pack<L>(Jw[0]);
-        const PW f2 = own ^ Zm ^ pack<L>(Jw[1]);
-        const PW f3 = own ^ Yp ^ pack<L>(Jw[2]);
-        const PW f4 = own ^ Ym ^ pack<L>(Jw[3]);
-        const PW f5 = own ^ O ^ pack<L>(Jw[4]);
-        const PW f6 = own ^ Xo ^ pack<L>(Jw[5]);
-        // Bit-sliced u = f1 + ... + f6, delivered as the level step m = 3 - u in 3-bit two's
-        // complement: m = (7 - u) ^ 4, i.e. bits (~u0, ~u1, u2).
-        const PW s1 = f1 ^ f2 ^ f3, k1 = (f1 & f2) | (f3 & (f1 ^ f2));
-        const PW s2 = f4 ^ f5 ^ f6, k2 = (f4 & f5) | (f6 & (f4 ^ f5));
-        const PW t0 = s1 & s2;
-        uint32_t m0[NWP], m1[NWP], m2[NWP];
-        unpack<L>(~(s1 ^ s2), m0);
-        unpack<L>(~(k1 ^ k2 ^ t0), m1);
-        unpack<L>((k1 & k2) | (t0 & (k1 ^ k2)), m2);
-        // Byte-interleave: V[g8] = (0, m0.byte, m1.byte, m2.byte). For the site at bit b of
-        // that byte, (V & (0x01010100 << b)) * (2^(26-b) + 2^(19-b) + 2^(12-b)) puts its three
-        // bits at 2^34, 2^35, 2^36 and every other partial product at another single bit
-        // (no carries), so bits 2..4 of the high word are m & 7.
-        uint32_t V[NB];
-#pragma unroll
-        for (int g8 = 0; g8 < NB; ++g8) {
-          const int w = g8 >> 2;
-          const uint32_t bsel = (uint32_t)(g8 & 3);
-          // perm selector bytes: 0x0c -> 0x00; 0..3 pick src1 bytes, 4..7 pick src0 bytes
-          const uint32_t lo = __builtin_amdgcn_perm(m1[w], m0[w], 0x0c00000cu | (bsel << 8) | ((4u + bsel) << 16));
-          V[g8] = __builtin_amdgcn_perm(m2[w], lo, 0x00020100u | ((4u + bsel) << 24));
-          asm volatile("" : "+v"(V[g8]));
-        }
-
-        const uint32_t ctr0 = (uint32_t)(c * L + z) << 8;
+        for (int w = 0; w < NWP; ++w) Cw[w] = lat(c, w)[z];
         const uint64_t tau_blk = tau0 + (uint64_t)(c * (N / 2) + z * Q);
-        // m & 7 of site q in bits 2..4 (sign at bit 4) of a product high word
-        auto gather = [&](int q) __attribute__((always_inline)) -> uint32_t {
-          const int y = q / H, j = q % H;
-          const int p = y * FB + j, g8 = p >> 3, bb = p & 7;
-          // (2^26 + 2^19 + 2^12) >> bb: eight distinct constants in all
-          return __umulhi(V[g8] & (0x01010100u << bb), 0x04081000u >> bb);
-        };
-        auto lookup = [&](uint32_t hi, int Rv) __attribute__((always_inline)) -> uint32_t {
-          // Rv is a multiple of 32 in [0, Bmax]; (hi & 0x1c) is 4 (m & 7)
-          return *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)((hi & 0x1cu) | (uint32_t)Rv);
-        };
         // Acceptance bits are shifted into F in site order, with a zero for every bit of a
         // field beyond the row's H sites, and applied to the plane-colour string once per word.
         uint32_t F = 0;
         int Bq[4];
-        uint32_t hi_cur = gather(0);
-        uint32_t th_cur = lookup(hi_cur, R);
-        uint32_t p_rej = th_cur, p_acc = th_cur;   // speculative pair of the current site
-        uint32_t addr_cur = (hi_cur & 0x1cu) | (uint32_t)R;
+        // speculative form: the pair for site 0 of the block is loaded at the block's start
+        uint32_t p_rej = 0, p_acc = 0;
         int Racc_prev = R;
-        // Random words of the next group are generated round by round between this group's
-        // attempts: each attempt issues its table read, then runs generator rounds and the next
-        // gather (independent of the read) before it waits for the threshold, so that the read's
-        // latency is covered by useful work even with a single wave per SIMD. Scheduling barriers
-        // keep that order.
-        constexpr int NG = (Q + 3) / 4;
-        PhiloxRun pr{ctr0, (uint32_t)t, real_id, ctr3};
-        philox_rounds<0, 10>(pr, kv);
-        uint32_t th_pt = 0;
-        if constexpr (PT) th_pt = th_cur;
+        if constexpr (SPEC && !PT) {
+          hi_cur = gather(Vc, 0);
+          p_rej = p_acc = lookup(hi_cur, R);
+        }
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
           const u32x4 rnd = {{pr.c0, pr.c1, pr.c2, pr.c3}};
-          if (g + 1 < NG) pr = PhiloxRun{ctr0 | (uint32_t)(g + 1), (uint32_t)t, real_id, ctr3};
+          // the next group: in this block, the next block, the other colour or the next sweep
+          if (g + 1 < NG) pr = group_ctr(c, z, g + 1, t);
+          else if (has_next) pr = group_ctr(c, z + 1, 0, t);
+          else if (c == 0) pr = group_ctr(1, 0, 0, t);
+          else pr = group_ctr(0, 0, 0, t + 1);
+          const int n_att = (4 * g + 4 <= Q) ? 4 : Q - 4 * g;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int q = 4 * g + i;
@@ -436,63 +462,55 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
             const int p = y * FB + j, w = p >> 5;
             if constexpr (SPEC && !PT) {
               const uint32_t rc = min(rnd.v[i], 0xFFFFFFFEu);
-              if (g + 1 < NG) {
-                if (i == 0) philox_rounds<0, 3>(pr, kv);
-                if (i == 1) philox_rounds<3, 5>(pr, kv);
-                if (i == 2) philox_rounds<5, 8>(pr, kv);
-                if (i == 3) philox_rounds<8, 10>(pr, kv);
-              }
+              if (i == 0) philox_rounds<0, 3>(pr, kv);
+              if (i == 1) philox_rounds<3, 5>(pr, kv);
+              if (i == 2) philox_rounds<5, 8>(pr, kv);
+              if (i == 3) philox_rounds<8, 10>(pr, kv);
               // thresholds of site q+1 for both outcomes of q are loaded before q is decided; the
               // threshold of site q is picked from the pair loaded one site earlier
               const int Bacc = B + __builtin_amdgcn_sbfe((int)hi_cur, 2, 3) * 32;
               const int Racc = clamp_row(Bacc, Bmax);
               uint32_t hi_next = 0, n_rej = 0, n_acc = 0;
               if (q + 1 < Q) {
-                hi_next = gather(q + 1);
+                hi_next = gather(Vc, q + 1);
                 n_rej = lookup(hi_next, R);
                 n_acc = lookup(hi_next, Racc);
               }
-              th_cur = (R == Racc_prev) ? p_acc : p_rej;
+              const uint32_t th_cur = (R == Racc_prev) ? p_acc : p_rej;
               accept_level_spec(rc, th_cur, Bacc, Racc, B, R, F);
               p_rej = n_rej;
               p_acc = n_acc;
               Racc_prev = Racc;
               hi_cur = hi_next;
             } else {
-              // (1) the threshold read: multicanonical, at the address the previous decision
-              //     computed; tempering, the next site's (the row is fixed), so that it is in
-              //     flight one attempt ahead
-              uint32_t th;
+              // (1) the threshold of this site, read earlier (multicanonical: by the previous
+              //     decision, at the address it computed; tempering: the row is fixed, so the
+              //     next site's read is issued here, one attempt ahead)
+              const uint32_t th = th_fly;
               uint32_t hi_next = 0;
+              if (q + 1 < Q) hi_next = gather(Vc, q + 1);
+              else if (has_next) hi_next = gather(Vn, 0);
               if constexpr (PT) {
-                th = th_pt;
-                if (q + 1 < Q) {
-                  hi_next = gather(q + 1);
-                  th_pt = lookup(hi_next, R);
-                }
-              } else {
-                th = *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr_cur;
+                if (q + 1 < Q || has_next) th_fly = lookup(hi_next, R);
               }
-              // (2) independent work: generator rounds of the next group, next gather, clamp. Empty
-              //     volatile statements pin the order: they are ordered with the read and the
-              //     decision, and the rounds' inputs and outputs pass through them.
+              // (2) independent work: generator rounds of the next group and the clamp. Empty
+              //     volatile statements pin the order: they are ordered with the decision, and
+              //     the rounds' inputs and outputs pass through them.
               asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
-              if (g + 1 < NG) {
-                if (i == 0) philox_rounds<0, 3>(pr, kv);
-                if (i == 1) philox_rounds<3, 5>(pr, kv);
-                if (i == 2) philox_rounds<5, 8>(pr, kv);
-                if (i == 3) philox_rounds<8, 10>(pr, kv);
-              }
-              if constexpr (!PT) {
-                if (q + 1 < Q) hi_next = gather(q + 1);
-              }
+              if (i == 0) philox_rounds<0, 3>(pr, kv);
+              if (i == 1) philox_rounds<3, 5>(pr, kv);
+              if (i == 2) philox_rounds<5, 8>(pr, kv);
+              if (i == 3) philox_rounds<8, 10>(pr, kv);
               const uint32_t rc = min(rnd.v[i], 0xFFFFFFFEu);
               asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
-              // (3) the decision (and the next site's table address)
+              // (3) the decision, the next site's table address and (multicanonical) its read,
+              //     issued before the bookkeeping and flips that follow
               if constexpr (PT) {
                 accept_energy(rc, th, hi_cur, E, F);
               } else {
                 accept_level(rc, th, hi_cur, hi_next, vBmax, B, R, F, addr_cur);
+                if (q + 1 < Q || has_next)
+                  th_fly = *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr_cur;
               }
               hi_cur = hi_next;
             }
@@ -507,9 +525,13 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
               F <<= (FB - H);
             }
           }
+          // a short last group: the generator rounds its missing attempts would have run
+          if (n_att == 1) philox_rounds<3, 10>(pr, kv);
+          if (n_att == 2) philox_rounds<5, 10>(pr, kv);
+          if (n_att == 3) philox_rounds<8, 10>(pr, kv);
           if constexpr (!PT) {
             // Did an attempt of this group leave the window? Then replay the group exactly.
-            const int last = (4 * g + 3 < Q) ? 3 : (Q - 1) - 4 * g;
+            const int last = n_att - 1;
             int bmin = Bq[0], bmax = Bq[0];
 #pragma unroll
             for (int k = 1; k < 4; ++k) {
@@ -529,6 +551,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
         }
 #pragma unroll
         for (int w = 0; w < NWP; ++w) lat(c, w)[z] = Cw[w];
+        if (has_next) {
+#pragma unroll
+          for (int k = 0; k < NB; ++k) Vc[k] = Vn[k];
+        }
       }
     }
     if constexpr (PT) {
@@ -571,9 +597,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     } else {
       // end of sweep: histogram (on chip) and trace
       const int k = (B >> 5) + row0;
-      if ((uint32_t)k < (uint32_t)K)  // always true for exact energies
-        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(uintptr_t)(hbase + 4u * (uint32_t)k), 1u,
+      const uint32_t kh = (uint32_t)(k - hlo);
+      if (kh < (uint32_t)hn && k < K)
+        __hip_atomic_fetch_add((__attribute__((address_space(3))) uint32_t*)(uintptr_t)(hbase + 4u * kh), 1u,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else if ((uint32_t)k < (uint32_t)K)  // always true for exact energies
+        atomicAdd(A.hist + RI.level_off + k, 1ULL);
       if (t - A.trace_t0 < (uint64_t)A.trace_cap)
         A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
     }
@@ -605,9 +634,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   } else {
     // the launch's histogram counts (at most 64 walkers x 2^20 sweeps per level)
     __syncthreads();
-    for (int e = threadIdx.x; e < K; e += 64) {
+    for (int e = threadIdx.x; e < hn; e += 64) {
       const uint32_t c = (uint32_t)lds_load_i32(hbase + 4u * (uint32_t)e);
-      if (c) atomicAdd(A.hist + RI.level_off + e, (unsigned long long)c);
+      if (c) atomicAdd(A.hist + RI.level_off + hlo + e, (unsigned long long)c);   // c > 0: hlo + e < K
     }
     A.ws.E[gw] = e_base + 4 * ((B >> 5) + row0);
     A.ws.E_min[gw] = e_base + 4 * ((tr.Bmin >> 5) + row0);
@@ -675,33 +704,63 @@ static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, h
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t launch_L(const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec, bool pt,
-                           hipStream_t s) {
-  const size_t jb = (size_t)jk_words(L) * 4;
-  if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
-  const size_t lds = (size_t)lds_rows * 32 + jb + (size_t)hist_levels * 4;   // table, couplings, histogram
-  return spec ? launch_LS<L, true, false>(a, n_waves, lds, s) : launch_LS<L, false, false>(a, n_waves, lds, s);
+// Levels kept on chip below the table rows and above them when the histogram is a window.
+constexpr int kHistMargin = 64;
+
+// The histogram's extent for a launch: every level of the realization when that leaves as many
+// workgroups resident per CU as the window would (capped at the ones the launch needs), else the
+// window [row0 - kHistMargin, row0 + rows + kHistMargin).
+struct HistPlan {
+  int margin, n;
+  size_t lds;
+};
+
+static HistPlan plan_hist(const void* f, size_t base_lds, int rows, int K, int want_blocks, int mode) {
+  const HistPlan full{K, K, base_lds + (size_t)K * 4};
+  const int nw = std::min(K, rows + 2 * kHistMargin);
+  const HistPlan win{kHistMargin, nw, base_lds + (size_t)nw * 4};
+  if (mode == 1) return win;
+  if (mode == 2) return full;
+  if (mode == 3) return HistPlan{0, std::min(K, rows), base_lds + (size_t)std::min(K, rows) * 4};
+  int occ_full = 0, occ_win = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_full, f, 64, full.lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_win, f, 64, win.lds) != hipSuccess)
+    return win;
+  return occ_full >= std::min(occ_win, want_blocks) ? full : win;
 }
 
-static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec, bool pt,
-                             hipStream_t s) {
+template <int L>
+static hipError_t launch_L(SweepArgs a, int n_waves, int lds_rows, int hist_levels, int n_cu, int hist_mode, bool spec,
+                           bool pt, hipStream_t s) {
+  const size_t jb = (size_t)jk_words(L) * 4;
+  if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
+  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps<L, true, false>)
+                       : reinterpret_cast<const void*>(&k_sweeps<L, false, false>);
+  const int want = (n_waves + n_cu - 1) / std::max(n_cu, 1);
+  const HistPlan h = plan_hist(f, (size_t)lds_rows * 32 + jb, lds_rows, hist_levels, want, hist_mode);   // table, couplings
+  a.hist_margin = h.margin;
+  a.hist_n = h.n;
+  return spec ? launch_LS<L, true, false>(a, n_waves, h.lds, s) : launch_LS<L, false, false>(a, n_waves, h.lds, s);
+}
+
+static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
+                             int hist_mode, bool spec, bool pt, hipStream_t s) {
   switch (L) {
-    case 2: return launch_L<2>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
-    case 4: return launch_L<4>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
-    case 6: return launch_L<6>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
-    case 8: return launch_L<8>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
-    case 10: return launch_L<10>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
-    case 12: return launch_L<12>(a, n_waves, lds_rows, hist_levels, spec, pt, s);
+    case 2: return launch_L<2>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
+    case 4: return launch_L<4>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
+    case 6: return launch_L<6>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
+    case 8: return launch_L<8>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
+    case 10: return launch_L<10>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
+    case 12: return launch_L<12>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
 
-hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, bool spec,
-                              hipStream_t s) {
-  return launch_any(L, a, n_waves, lds_rows, hist_levels, spec, false, s);
+hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
+                              int hist_mode, bool spec, hipStream_t s) {
+  return launch_any(L, a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, false, s);
 }
 
 template <bool SPEC>
@@ -723,31 +782,35 @@ static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n
 }
 
 // LDS of the persistent kernel: the largest table, the couplings of the largest lattice and the
-// largest histogram of the batch.
-static size_t queue_lds_bytes(int lds_rows, int hist_levels) {
-  return (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4 + (size_t)hist_levels * 4;
+// histogram planned for the largest table and level count of the batch.
+static HistPlan queue_plan(bool spec, int lds_rows, int hist_levels, int want_blocks, int mode) {
+  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
+                       : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
+  return plan_hist(f, (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4, lds_rows, hist_levels, want_blocks, mode);
 }
 
-int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels) {
+int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode) {
   int n = 0;
   const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
                        : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, queue_lds_bytes(lds_rows, hist_levels)) != hipSuccess)
-    return 0;
+  const HistPlan h = queue_plan(spec, lds_rows, hist_levels, 1 << 20, hist_mode);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, h.lds) != hipSuccess) return 0;
   return n;
 }
 
-hipError_t launch_muca_queue(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
-                             int lds_rows, int hist_levels, bool spec, hipStream_t s) {
+hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uint32_t* counter, int grid, int n_cu,
+                             int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s) {
   if (grid < 1 || n_items < 0) return hipErrorInvalidValue;
-  const size_t lds = queue_lds_bytes(lds_rows, hist_levels);
-  return spec ? launch_queue_S<true>(a, order, n_items, counter, grid, lds, s)
-              : launch_queue_S<false>(a, order, n_items, counter, grid, lds, s);
+  const HistPlan h = queue_plan(spec, lds_rows, hist_levels, (grid + n_cu - 1) / std::max(n_cu, 1), hist_mode);
+  a.hist_margin = h.margin;
+  a.hist_n = h.n;
+  return spec ? launch_queue_S<true>(a, order, n_items, counter, grid, h.lds, s)
+              : launch_queue_S<false>(a, order, n_items, counter, grid, h.lds, s);
 }
 
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s) {
   if (a.pt_M < 2 || a.pt_M > kMaxReplicas || (a.pt_M & (a.pt_M - 1)) != 0 || a.pt_D < 1) return hipErrorInvalidValue;
-  return launch_any(L, a, n_waves, 1, 0, false, true, s);
+  return launch_any(L, a, n_waves, 1, 0, 1, 0, false, true, s);
 }
 
 }  // namespace nfm

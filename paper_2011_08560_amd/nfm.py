@@ -43,8 +43,8 @@ REC_DTYPE = np.dtype([("k_lo", np.int32), ("k_top", np.int32), ("profile", np.in
 RT_SUMMARY_DTYPE = np.dtype([("tau_pop", np.float64), ("trips", np.uint64), ("n_used", np.int32),
                              ("n_censored", np.int32)], align=True)
 PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
-TUNING_FIELDS = ("speculate", "sweeps_per_launch", "schedule", "waves_per_cu")
-TUNE_RESULT_DTYPE = np.dtype([("tuning", np.int32, (4,)), ("attempts_per_s", np.float64)], align=True)
+TUNING_FIELDS = ("speculate", "sweeps_per_launch", "schedule", "waves_per_cu", "hist")
+TUNE_RESULT_DTYPE = np.dtype([("tuning", np.int32, (5,)), ("attempts_per_s", np.float64)], align=True)
 
 _lib = None
 
@@ -421,12 +421,13 @@ class Batch:
                                                 info.ctypes.data), "rec_set_state")
 
     # launch tuning
-    def set_tuning(self, speculate: int = -1, sweeps_per_launch: int = 0, schedule: int = 0, waves_per_cu: int = 0):
-        t = np.array([speculate, sweeps_per_launch, schedule, waves_per_cu], np.int32)
+    def set_tuning(self, speculate: int = -1, sweeps_per_launch: int = 0, schedule: int = 0, waves_per_cu: int = 0,
+                   hist: int = 0):
+        t = np.array([speculate, sweeps_per_launch, schedule, waves_per_cu, hist], np.int32)
         self._check(self._lib.nfm_set_tuning(self.ctx, t.ctypes.data), "set_tuning")
 
     def get_tuning(self) -> dict:
-        t = np.zeros(4, np.int32)
+        t = np.zeros(5, np.int32)
         self._check(self._lib.nfm_get_tuning(self.ctx, t.ctypes.data), "get_tuning")
         return dict(zip(TUNING_FIELDS, (int(x) for x in t)))
 
@@ -435,7 +436,7 @@ class Batch:
         apply the fastest. Returns (best tuning dict, list of (tuning dict, attempts/s))."""
         res = np.zeros(max_results, TUNE_RESULT_DTYPE)
         n = C.c_int32()
-        best = np.zeros(4, np.int32)
+        best = np.zeros(5, np.int32)
         path = cache_path.encode() if cache_path else None
         self._check(self._lib.nfm_autotune(self.ctx, calib_sweeps, path, res.ctypes.data if max_results else None,
                                            max_results, C.byref(n), best.ctypes.data), "autotune")

@@ -71,11 +71,13 @@ def test_spins_roundtrip_across_sizes(nfm, orc):
     b.close()
 
 
-CONFIGS = [dict(schedule=1, speculate=0, sweeps_per_launch=0, waves_per_cu=0),
-           dict(schedule=1, speculate=1, sweeps_per_launch=7, waves_per_cu=0),
-           dict(schedule=1, speculate=0, sweeps_per_launch=16, waves_per_cu=1),
-           dict(schedule=1, speculate=1, sweeps_per_launch=0, waves_per_cu=3),
-           dict(schedule=0, speculate=1, sweeps_per_launch=9, waves_per_cu=0)]
+# hist: 0 automatic, 1 window, 2 every level, 3 the table rows alone (most counts outside LDS)
+CONFIGS = [dict(schedule=1, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0),
+           dict(schedule=1, speculate=1, sweeps_per_launch=7, waves_per_cu=0, hist=1),
+           dict(schedule=1, speculate=0, sweeps_per_launch=16, waves_per_cu=1, hist=3),
+           dict(schedule=1, speculate=1, sweeps_per_launch=0, waves_per_cu=3, hist=2),
+           dict(schedule=0, speculate=1, sweeps_per_launch=9, waves_per_cu=0, hist=3),
+           dict(schedule=0, speculate=0, sweeps_per_launch=11, waves_per_cu=0, hist=1)]
 
 
 def test_schedules_give_identical_results(nfm, orc):
@@ -95,10 +97,11 @@ def test_schedules_give_identical_results(nfm, orc):
         b.close()
 
 
-def test_queue_matches_oracle(nfm, orc):
+@pytest.mark.parametrize("hist", [0, 3])
+def test_queue_matches_oracle(nfm, orc, hist):
     n, first = 24, 5
     b = _batch(nfm, orc, MIX, 0, first=first)
-    b.set_tuning(schedule=1, speculate=1, sweeps_per_launch=10)
+    b.set_tuning(schedule=1, speculate=1, sweeps_per_launch=10, hist=hist)
     b.run_sweeps(n)
     ws = b.read_walkers()
     H = b.read_histograms()
@@ -134,7 +137,7 @@ def test_autotune_restores_state_and_caches(nfm, orc, tmp_path):
     _same(_state(b), before)
     assert b.sweep_counter == t_before
     text = open(cache).read().split()
-    assert len(text) == 5 and [int(x) for x in text[1:]] == [best[k] for k in nfm.TUNING_FIELDS]
+    assert len(text) == 6 and [int(x) for x in text[1:]] == [best[k] for k in nfm.TUNING_FIELDS]
     best2, table2 = b.autotune(calib_sweeps=32, cache_path=cache)    # cached: no measurement
     assert best2 == best and table2 == []
     b.run_sweeps(20)
