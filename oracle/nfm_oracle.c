@@ -161,11 +161,18 @@ int32_t orc_unsatisfied(int32_t L, const int8_t* J, const int8_t* S, int32_t i) 
  * exp(-(d(k+m)+...+d(k-1))) for m < 0, summed in ascending j. Outside the
  * known range: d(j) = 0 for j >= k_top (W constant above the top energy) and
  * d(j) = d(k_lo) for j < k_lo (lowest known step continued). The probability
- * is stored as thr = floor(x 2^32), or 0xFFFFFFFF (always accept) if x >= 1.  */
+ * is stored as thr = floor(x 2^32), or 0xFFFFFFFF (always accept) if x >= 1.
+ * An attempt with 32-bit random word r is accepted iff thr = 0xFFFFFFFF or
+ * r < max(thr, 1): probabilities are quantised down to multiples of 2^-32,
+ * with 2^-32 as the least (no move is forbidden outright).                  */
 static double step_logw(const double* lnw, int32_t k_lo, int32_t k_top, int32_t j) {
   if (j < k_lo) j = k_lo;
   if (j >= k_top) return 0.0;
   return lnw[j + 1 - k_lo] - lnw[j - k_lo];
+}
+
+int32_t orc_metropolis_accept(uint32_t r, uint32_t thr) {
+  return (thr == 0xFFFFFFFFu) || (r < (thr ? thr : 1u));
 }
 
 static uint32_t quantize(double x) {
@@ -277,7 +284,7 @@ int32_t orc_muca_sweeps(int32_t L, const int8_t* J, int8_t* S, orc_walker* w,
       uint32_t th = thr[row * 8 + u];
       uint32_t r = philox_word(slot_ctr[i], (uint32_t)t, real_id,
                                (walker << 8) | ORC_TAG_ACC, walker_seed, slot_which[i]);
-      int accept = (th == 0xFFFFFFFFu) || (r < th);
+      int accept = orc_metropolis_accept(r, th);
       if (accept) {
         S[i] = (int8_t)(-S[i]);
         w->E += 12 - 4 * u;
@@ -651,7 +658,7 @@ int32_t orc_pt_sweeps(int32_t L, const int8_t* J, int32_t M, int8_t* S, orc_walk
         uint32_t th = metro[slot[c] * 8 + u];
         uint32_t r = philox_word(slot_ctr[i], (uint32_t)t, real_id, (walker << 8) | ORC_TAG_PT,
                                  walker_seed, slot_which[i]);
-        if (th == 0xFFFFFFFFu || r < th) {
+        if (orc_metropolis_accept(r, th)) {
           Sc[i] = (int8_t)(-Sc[i]);
           w[c].E += 12 - 4 * u;
         }

@@ -67,6 +67,10 @@ int32_t orc_table_rows(int32_t K, int32_t k_lo, int32_t k_top, int32_t* row0);
 int32_t orc_build_thresholds(int32_t K, const double* lnw, int32_t k_lo, int32_t k_top,
                              uint32_t* thr, int32_t* row0, int32_t* rows);
 
+/* Metropolis acceptance of an attempt with random word r and stored threshold thr
+ * (Eq. (2) with quantised probabilities): thr = 0xFFFFFFFF or r < max(thr, 1). */
+int32_t orc_metropolis_accept(uint32_t r, uint32_t thr);
+
 /* Round-trip / minimum bookkeeping after one attempt (stamp tau, energy E). */
 void orc_track(orc_walker* w, int32_t E, int32_t e_bot, int32_t e_top, uint64_t tau);
 

@@ -83,6 +83,8 @@ def lib():
         L.orc_muca_sweeps.argtypes = [i32, P(np.int8), P(np.int8), C.c_void_p, P(np.uint32), i32, i32,
                                       i32, i32, u64, u32, u32, u64, u64, C.c_void_p, C.c_void_p, i32]
         L.orc_muca_sweeps.restype = i32
+        L.orc_metropolis_accept.argtypes = [u32, u32]
+        L.orc_metropolis_accept.restype = i32
         L.orc_brute_dos.argtypes = [i32, P(np.int8), P(np.uint64)]
         L.orc_brute_dos.restype = i32
         L.orc_power_profile.argtypes = [dbl, dbl, dbl, dbl]
@@ -190,6 +192,12 @@ def new_walkers(n: int, E0) -> np.ndarray:
 
 def track(w: np.ndarray, E: int, e_bot: int, e_top: int, tau: int) -> None:
     lib().orc_track(w.ctypes.data, E, e_bot, e_top, tau)
+
+
+def metropolis_accept(r, thr):
+    """Acceptance of an attempt with random word r under stored threshold thr (Eq. (2),
+    probabilities quantised down to multiples of 2^-32 with 2^-32 as the least)."""
+    return bool(lib().orc_metropolis_accept(int(r), int(thr)))
 
 
 def muca_sweeps(L, J, S, w, thr, row0, e_bot, e_top, walker_seed, real_id, walker,

@@ -100,7 +100,7 @@ def _exact_sweep_matrix(L, J, thr, row0):
             k = (Es[s] - eb) // 4
             r = min(max(k - row0, 0), rows - 1)
             th = int(thr[r, U[s, i]])
-            p = 1.0 if th == FULL else th / 2.0 ** 32
+            p = 1.0 if th == FULL else max(th, 1) / 2.0 ** 32
             T[s, s ^ (1 << i)] += p
             T[s, s] += 1.0 - p
         M = M @ T
@@ -267,6 +267,17 @@ def test_round_trip_tracker_synthetic(orc):
         orc.track(w, e, e_bot, e_top, s)
     assert w["rt_count"][0] == 1 and w["t_first"][0] == 3 and w["t_last"][0] == 6
     assert w["new_min"][0] == 0
+
+
+def test_acceptance_rule(orc):
+    """Acceptance of an attempt: probability thr / 2^32 (r < thr for r uniform on 32 bits),
+    always for the all-accept value, and never below 2^-32 (thr = 0 accepts r = 0 only)."""
+    acc = orc.metropolis_accept
+    assert acc(0, FULL) and acc(FULL, FULL) and acc(FULL - 1, FULL)
+    assert acc(4, 5) and not acc(5, 5) and not acc(FULL, 5)
+    assert acc(0, 1) and not acc(1, 1)
+    assert acc(0, 0) and not acc(1, 0) and not acc(FULL, 0)
+    assert acc(FULL - 2, FULL - 1) and not acc(FULL - 1, FULL - 1)
 
 
 def test_acceptance_word_layout(orc):
