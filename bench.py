@@ -31,8 +31,11 @@ sys.path.insert(0, ROOT)
 # Philox4x32-10 share 10 (2.5 rounds x (2 wide products + 2 three-input xors)), neighbour
 # count 1, table address 2, acceptance 2, spin/energy update 2, bookkeeping check 1.
 ALG_OPS_PER_ATTEMPT = 18.0
-# MI355X integer VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per cycle).
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X 32-bit vector ALU peak from its unit counts and clock: 256 CUs x 4 SIMD x 32 lanes x
+# 2.4 GHz = 78.6 T lane-ops/s, the rate behind the published FP32 vector figure (157.3 TFLOP/s,
+# an FMA counting two). Measured on the chip, simple integer ops reach about 20-23 lanes per
+# clock per SIMD, 32x32-bit products 8-14, and a lone wave issues one instruction per ~4.7 cycles.
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 
 CONFIGS = {
     # name: (mix [(L, realizations)], walkers per realization, sweeps per step, description)

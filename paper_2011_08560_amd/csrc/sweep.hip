@@ -144,7 +144,8 @@ __device__ __forceinline__ void lds_store_i32(uint32_t byte_addr, int v) {
 }
 
 // Acceptance of one attempt and its effect on the state, as one instruction sequence: the
-// comparison sets VCC, which then selects the new state and is shifted into the flip word F
+// comparison r <= th' of the random word with the on-chip threshold (th' = thr - 1, or 0 for
+// thr = 0, or 2^32 - 1 for always, so that r <= th' <=> thr = 2^32 - 1 or r < max(thr, 1)) sets VCC, which then selects the new state and is shifted into the flip word F
 // (F = 2F + accepted). The two instructions between the comparison and the first reader of
 // VCC are the distance the hardware needs between a VALU write of VCC and a VALU read of it.
 //   level form:  B (row offset of the level, 32 per level) += 32 m on acceptance
@@ -155,7 +156,7 @@ __device__ __forceinline__ void accept_level(uint32_t rc, uint32_t th, uint32_t 
                                              int& R, uint32_t& F, uint32_t& addr) {
   int m, Bacc, Bn, Rn;
   uint32_t Fn, an;
-  asm volatile("v_cmp_lt_u32_e32 vcc, %[rc], %[th]\n\t"
+  asm volatile("v_cmp_le_u32_e32 vcc, %[rc], %[th]\n\t"
       "v_bfe_i32 %[m], %[hi], 2, 3\n\t"
       "v_lshl_add_u32 %[Bacc], %[m], 5, %[B]\n\t"
       "v_cndmask_b32_e32 %[Bn], %[B], %[Bacc], vcc\n\t"
@@ -171,10 +172,29 @@ __device__ __forceinline__ void accept_level(uint32_t rc, uint32_t th, uint32_t 
   addr = an;
 }
 
+// Expanded table (every level has its own row on chip): the row is the level, no clamp.
+__device__ __forceinline__ void accept_level_xt(uint32_t rc, uint32_t th, uint32_t hi, uint32_t hn, int& B,
+                                                uint32_t& F, uint32_t& addr) {
+  int m, Bacc, Bn;
+  uint32_t Fn, an;
+  asm volatile("v_cmp_le_u32_e32 vcc, %[rc], %[th]\n\t"
+      "v_bfe_i32 %[m], %[hi], 2, 3\n\t"
+      "v_lshl_add_u32 %[Bacc], %[m], 5, %[B]\n\t"
+      "v_cndmask_b32_e32 %[Bn], %[B], %[Bacc], vcc\n\t"
+      "v_addc_co_u32_e32 %[Fn], vcc, %[F], %[F], vcc\n\t"
+      "v_and_or_b32 %[an], %[hn], 28, %[Bn]"
+      : [Bn] "=&v"(Bn), [Fn] "=&v"(Fn), [m] "=&v"(m), [Bacc] "=&v"(Bacc), [an] "=&v"(an)
+      : [rc] "v"(rc), [th] "v"(th), [hi] "v"(hi), [hn] "v"(hn), [B] "v"(B), [F] "v"(F)
+      : "vcc");
+  B = Bn;
+  F = Fn;
+  addr = an;
+}
+
 __device__ __forceinline__ void accept_energy(uint32_t rc, uint32_t th, uint32_t hi, int& E, uint32_t& F) {
   int m, Eacc, En;
   uint32_t Fn;
-  asm volatile("v_cmp_lt_u32_e32 vcc, %[rc], %[th]\n\t"
+  asm volatile("v_cmp_le_u32_e32 vcc, %[rc], %[th]\n\t"
       "v_bfe_i32 %[m], %[hi], 2, 3\n\t"
       "v_lshl_add_u32 %[Eacc], %[m], 2, %[E]\n\t"
       "v_cndmask_b32_e32 %[En], %[E], %[Eacc], vcc\n\t"
@@ -192,7 +212,7 @@ __device__ __forceinline__ void accept_level_spec(uint32_t rc, uint32_t th, int 
                                                   uint32_t& F) {
   int Bn, Rn;
   uint32_t Fn;
-  asm("v_cmp_lt_u32_e32 vcc, %[rc], %[th]\n\t"
+  asm("v_cmp_le_u32_e32 vcc, %[rc], %[th]\n\t"
       "s_nop 1\n\t"
       "v_cndmask_b32_e32 %[Bn], %[B], %[Bacc], vcc\n\t"
       "v_cndmask_b32_e32 %[Rn], %[R], %[Racc], vcc\n\t"
@@ -215,7 +235,10 @@ __device__ __forceinline__ int clamp_row(int B, int Bmax) {
 // PT = true: parallel tempering (Sec. II, Eq. (8)); the walkers of a realization form sets of
 // M configurations, the row is the configuration's temperature slot, and after every sweep the
 // slots (s, s+1) with s = t (mod 2) try an exchange.
-template <int L, bool SPEC, bool PT>
+// XT (multicanonical, no speculation): the table is expanded on chip to one row per level of
+// the realization (rows outside the stored range repeat its edge rows, as the clamp would), so
+// the row of a level is the level itself and the decision needs no clamp.
+template <int L, bool SPEC, bool PT, bool XT = false>
 __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   using G = Geo<L>;
   using PW = typename G::PW;
@@ -223,18 +246,20 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   constexpr int NB = (G::BITS + 7) / 8;  // bytes of a plane-colour string
   constexpr int kZUnroll = L <= 6 ? L : 1;
   static_assert(!(PT && SPEC), "the tempering row does not depend on the decision");
+  static_assert(!(XT && (PT || SPEC)), "the expanded table is for the plain multicanonical form");
   const int r = A.wave_real[wave];
   const int wl = A.wave_wl[wave] + (int)threadIdx.x;
   const RealInfo& RI = A.reals[r];
-  const int row0 = PT ? 0 : RI.row0, rows = PT ? A.pt_M : RI.rows;
   const int e_base = RI.e_base, walkers = RI.walkers, K = RI.K;
+  const int row0 = (PT || XT) ? 0 : RI.row0, rows = PT ? A.pt_M : (XT ? K : RI.rows);
   const int e_bot = RI.e_bot, e_top = RI.e_top;
   const uint32_t real_id = RI.real_id;
   const int64_t gw = RI.walker_off + wl;
 
   // LDS (the kernel's only LDS, so it starts at address 0):
   //   [0, rows*32)        threshold table, each row permuted from u-order to m-order: entry j
-  //                       holds the threshold of the step m = j (j < 4) or m = j - 8 (j > 4);
+  //                       holds the threshold of the step m = j (j < 4) or m = j - 8 (j > 4),
+  //                       as th' of the decision (r <= th');
   //   tempering only      energies by slot, exchange decisions, exchange counters (3 x 256 B);
   //   then                the realization's couplings in the kernel layout;
   //   multicanonical only the launch's histogram over a window of levels around the table rows
@@ -250,7 +275,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
       const int jj = e & 7;
       const int u = jj < 4 ? 3 - jj : (jj == 4 ? 7 : 11 - jj);
-      *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = gt[(e & ~7) + u];
+      int gr = e >> 3;   // row of the stored table
+      if constexpr (XT) gr = min(max(gr - RI.row0, 0), RI.rows - 1);
+      const uint32_t v = gt[gr * 8 + u];
+      const uint32_t vp = (v == 0xFFFFFFFFu) ? v : (v ? v - 1u : 0u);
+      *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = vp;
     }
     const uint32_t* jg = A.jk + RI.jk_off;
     for (int e = threadIdx.x; e < jk_words(L); e += 64) lds_store_i32(jbase + 4u * (uint32_t)e, (int)jg[e]);
@@ -461,7 +490,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
             const int y = q / H, j = q % H;
             const int p = y * FB + j, w = p >> 5;
             if constexpr (SPEC && !PT) {
-              const uint32_t rc = min(rnd.v[i], 0xFFFFFFFEu);
+              const uint32_t rc = rnd.v[i];
               if (i == 0) philox_rounds<0, 3>(pr, kv);
               if (i == 1) philox_rounds<3, 5>(pr, kv);
               if (i == 2) philox_rounds<5, 8>(pr, kv);
@@ -493,22 +522,29 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
               if constexpr (PT) {
                 if (q + 1 < Q || has_next) th_fly = lookup(hi_next, R);
               }
-              // (2) independent work: generator rounds of the next group and the clamp. Empty
-              //     volatile statements pin the order: they are ordered with the decision, and
-              //     the rounds' inputs and outputs pass through them.
-              asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
+              // (2) independent work: generator rounds of the next group. Empty volatile
+              //     statements pin the order: they are ordered with the decision, and the
+              //     rounds' outputs pass through the second one. The first takes only the words
+              //     the round's products do not read: a VALU read of a register an asm statement
+              //     wrote costs a wait state, and uniform words stay scalar.
+              asm volatile("" : "+v"(pr.c1), "+v"(pr.c3));
               if (i == 0) philox_rounds<0, 3>(pr, kv);
               if (i == 1) philox_rounds<3, 5>(pr, kv);
               if (i == 2) philox_rounds<5, 8>(pr, kv);
               if (i == 3) philox_rounds<8, 10>(pr, kv);
-              const uint32_t rc = min(rnd.v[i], 0xFFFFFFFEu);
+              const uint32_t rc = rnd.v[i];
               asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
               // (3) the decision, the next site's table address and (multicanonical) its read,
               //     issued before the bookkeeping and flips that follow
               if constexpr (PT) {
                 accept_energy(rc, th, hi_cur, E, F);
               } else {
-                accept_level(rc, th, hi_cur, hi_next, vBmax, B, R, F, addr_cur);
+                if constexpr (XT) {
+                  accept_level_xt(rc, th, hi_cur, hi_next, B, F, addr_cur);
+                  R = B;
+                } else {
+                  accept_level(rc, th, hi_cur, hi_next, vBmax, B, R, F, addr_cur);
+                }
                 if (q + 1 < Q || has_next)
                   th_fly = *(const __attribute__((address_space(3))) uint32_t*)(uintptr_t)addr_cur;
               }
@@ -648,11 +684,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   }
 }
 
-template <int L, bool SPEC, bool PT>
+template <int L, bool SPEC, bool PT, bool XT>
 __global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
   extern __shared__ uint32_t stab[];  // addressed from LDS address 0 by sweep_wave
   (void)stab;
-  sweep_wave<L, SPEC, PT>(A, (int)blockIdx.x);
+  sweep_wave<L, SPEC, PT, XT>(A, (int)blockIdx.x);
 }
 
 // Persistent multicanonical launch over a batch of mixed lattice sizes: each workgroup takes
@@ -688,19 +724,19 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-template <int L, bool SPEC, bool PT>
+template <int L, bool SPEC, bool PT, bool XT = false>
 static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, hipStream_t s) {
   // The kernel addresses its dynamic LDS block from address 0, which is only valid
   // when the compiler placed nothing else in LDS.
   static int checked = 0;
   if (!checked) {
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps<L, SPEC, PT>));
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps<L, SPEC, PT, XT>));
     if (e != hipSuccess) return e;
     if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     checked = 1;
   }
-  hipLaunchKernelGGL((k_sweeps<L, SPEC, PT>), dim3(n_waves), dim3(64), lds_bytes, s, a);
+  hipLaunchKernelGGL((k_sweeps<L, SPEC, PT, XT>), dim3(n_waves), dim3(64), lds_bytes, s, a);
   return hipGetLastError();
 }
 
@@ -734,10 +770,22 @@ static hipError_t launch_L(SweepArgs a, int n_waves, int lds_rows, int hist_leve
                            bool pt, hipStream_t s) {
   const size_t jb = (size_t)jk_words(L) * 4;
   if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
-  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps<L, true, false>)
-                       : reinterpret_cast<const void*>(&k_sweeps<L, false, false>);
+  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps<L, true, false, false>)
+                       : reinterpret_cast<const void*>(&k_sweeps<L, false, false, false>);
   const int want = (n_waves + n_cu - 1) / std::max(n_cu, 1);
   const HistPlan h = plan_hist(f, (size_t)lds_rows * 32 + jb, lds_rows, hist_levels, want, hist_mode);   // table, couplings
+  if (!spec && hist_mode == 0) {
+    // the expanded table (and every level of the histogram) when it costs no resident workgroups
+    const void* fx = reinterpret_cast<const void*>(&k_sweeps<L, false, false, true>);
+    const size_t lds_x = (size_t)hist_levels * 32 + jb + (size_t)hist_levels * 4;
+    int occ_x = 0, occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_x, fx, 64, lds_x) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 64, h.lds) == hipSuccess && occ_x >= std::min(occ, want)) {
+      a.hist_margin = hist_levels;
+      a.hist_n = hist_levels;
+      return launch_LS<L, false, false, true>(a, n_waves, lds_x, s);
+    }
+  }
   a.hist_margin = h.margin;
   a.hist_n = h.n;
   return spec ? launch_LS<L, true, false>(a, n_waves, h.lds, s) : launch_LS<L, false, false>(a, n_waves, h.lds, s);
