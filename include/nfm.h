@@ -337,6 +337,49 @@ nfm_status nfm_rt_stats(nfm_ctx* ctx, int32_t r0, int32_t count, uint64_t min_tr
                         nfm_rt_summary* host_summary);
 
 /* ---------------------------------------------------------------------------------------
+ * Round-trip-time statistics across realizations (Sec. IV). Host functions, no context, no
+ * device: inputs are per-realization mean round-trip times (nfm_rt_stats), all finite and > 0.
+ *
+ * Frechet distribution, Eq. (9): F(tau) = exp(-(1 + xi (tau - mu)/beta)^(-1/xi)) on
+ * tau >= mu - beta/xi, with beta > 0, xi > 0.
+ *   nfm_frechet_cdf: F(tau) (0 below the support).
+ *   nfm_frechet_quantile: Q(p), Eq. (13), p in (0, 1) (NaN outside).
+ *   nfm_frechet_mean: Eq. (11), mu + beta/xi (Gamma(1 - xi) - 1) for xi < 1, +inf otherwise.
+ *   nfm_frechet_quantile_mean: Eq. (14), the mean integral cut at Q(1 - eps) and not renormalized,
+ *     in closed form (mu - beta/xi)(1 - eps) + beta/xi Gamma(1 - xi, -ln(1 - eps)); eps in [0, 1)
+ *     (eps = 0 gives Eq. (11)).
+ *   nfm_upper_gamma: the upper incomplete gamma function Gamma(a, x) for real a and x > 0 (NaN
+ *     otherwise); for a <= 0 by Gamma(a, x) = (Gamma(a + 1, x) - x^a e^-x) / a from (0, 1], or
+ *     from E1 = Gamma(0, x).
+ *   nfm_frechet_fit: the parameters fitted to n >= 3 times (the paper fits "the CDF" without
+ *     naming the estimator): method 0 = maximum likelihood, 1 = least squares between F and the
+ *     plotting positions (i - 1/2)/n of the sorted times. *objective (may be NULL) receives the
+ *     minimised negative log-likelihood or sum of squares. NFM_EINVAL for bad input (message in
+ *     nfm_stats_last_error()).
+ *   nfm_relative_performance: r of Table I for paired samples (index i = the same disorder
+ *     realization under both methods): r_pop = mean(tau_m) / mean(tau_ref) and
+ *     r_eps = <tau>_eps(fit of tau_m) / <tau>_eps(fit of tau_ref), each with a jackknife error
+ *     from `blocks` contiguous blocks of realizations left out in turn (0 = one realization per
+ *     block); also the two full-sample fits. eps in (0, 1). */
+typedef struct {
+  double mu, beta, xi;
+} nfm_frechet;
+typedef struct {
+  double r_pop, r_pop_err, r_eps, r_eps_err;
+  nfm_frechet fit_m, fit_ref;
+  int32_t blocks, pad;
+} nfm_ratio;
+double nfm_frechet_cdf(const nfm_frechet* d, double tau);
+double nfm_frechet_quantile(const nfm_frechet* d, double p);
+double nfm_frechet_mean(const nfm_frechet* d);
+double nfm_frechet_quantile_mean(const nfm_frechet* d, double eps);
+double nfm_upper_gamma(double a, double x);
+nfm_status nfm_frechet_fit(const double* tau, int64_t n, int32_t method, nfm_frechet* fit, double* objective);
+nfm_status nfm_relative_performance(const double* tau_m, const double* tau_ref, int64_t n, double eps,
+                                    int32_t method, int32_t blocks, nfm_ratio* out);
+const char* nfm_stats_last_error(void);
+
+/* ---------------------------------------------------------------------------------------
  * Learned start of the weight iteration (not in the paper: a model that guesses the density of
  * states from the couplings, checked by the recursion of Sec. II, which remains the judge).
  *

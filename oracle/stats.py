@@ -1,0 +1,182 @@
+"""Oracle of the round-trip-time statistics (Sec. IV): test infrastructure, not product code.
+
+Written from the definitions: the Frechet CDF of Eq. (9), its density, the distribution mean of
+Eq. (10) and the quantile mean of Eq. (14) as the integrals they are defined by (mpmath
+quadrature), the quantile function of Eq. (13) as the inverse of Eq. (9), maximum-likelihood and
+least-squares fits as the optima of their objectives (scipy's optimizers as steps), and the
+relative performance r of Table I with a delete-a-block jackknife (the paper names the jackknife
+without its variant). Only the tests and the CPU leg of the benchmark use this module.
+"""
+from __future__ import annotations
+
+import math
+
+import mpmath
+import numpy as np
+from scipy import optimize, stats
+
+
+def support_lower(mu, beta, xi):
+    return mu - beta / xi
+
+
+def cdf(params, tau):
+    """Eq. (9): exp(-(1 + xi (tau - mu)/beta)^(-1/xi)); 0 below the support."""
+    mu, beta, xi = params
+    z = 1.0 + xi * (np.asarray(tau, dtype=np.float64) - mu) / beta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out = np.exp(-np.power(np.where(z > 0, z, 1.0), -1.0 / xi))
+    return np.where(z > 0, out, 0.0)
+
+
+def pdf(params, tau):
+    """dF/dtau of Eq. (9)."""
+    mu, beta, xi = params
+    z = 1.0 + xi * (np.asarray(tau, dtype=np.float64) - mu) / beta
+    zz = np.where(z > 0, z, 1.0)
+    out = (1.0 / beta) * np.power(zz, -1.0 - 1.0 / xi) * np.exp(-np.power(zz, -1.0 / xi))
+    return np.where(z > 0, out, 0.0)
+
+
+def quantile(params, p):
+    """Eq. (13): the inverse of Eq. (9), found by bisection on the CDF (not the printed form)."""
+    mu, beta, xi = params
+    lo = support_lower(mu, beta, xi)
+    hi = lo + beta
+    while cdf(params, hi) < p:
+        hi = lo + 2.0 * (hi - lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if cdf(params, mid) < p:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _mp_pdf(params):
+    mu, beta, xi = (mpmath.mpf(v) for v in params)
+
+    def f(t):
+        z = 1 + xi * (t - mu) / beta
+        if z <= 0:
+            return mpmath.mpf(0)
+        return (1 / beta) * z ** (-1 - 1 / xi) * mpmath.exp(-z ** (-1 / xi))
+    return f
+
+
+def quantile_mean(params, eps, dps=30):
+    """Eq. (14): the integral of tau f(tau) from the lower end of the support to Q(1 - eps), by
+    quadrature over log-spaced pieces (eps = 0: the distribution mean of Eq. (10), inf for xi >= 1)."""
+    mu, beta, xi = params
+    if eps == 0.0 and xi >= 1.0:
+        return math.inf
+    with mpmath.workdps(dps):
+        f = _mp_pdf(params)
+        lo = mpmath.mpf(support_lower(mu, beta, xi))
+        mu_m, beta_m, xi_m = (mpmath.mpf(v) for v in params)
+        if eps == 0.0:
+            hi = mpmath.inf
+        else:
+            hi = mu_m + beta_m / xi_m * ((-mpmath.log(1 - mpmath.mpf(eps))) ** (-xi_m) - 1)
+        # breakpoints: the bulk near the mode, then geometric steps through the tail
+        pts = [lo, lo + beta_m * mpmath.mpf("0.01"), lo + beta_m * mpmath.mpf("0.1"), lo + beta_m]
+        step = beta_m
+        while pts[-1] + step < (hi if hi != mpmath.inf else lo + beta_m * mpmath.mpf(10) ** 80):
+            step *= 4
+            pts.append(pts[-1] + step)
+        pts.append(hi)
+        val = mpmath.quad(lambda t: t * f(t), pts)
+        return float(val)
+
+
+def nll(params, tau):
+    """Negative log-likelihood of the sample under Eq. (9)'s density (inf outside the support)."""
+    mu, beta, xi = params
+    if beta <= 0 or xi <= 0:
+        return math.inf
+    z = 1.0 + xi * (np.asarray(tau, dtype=np.float64) - mu) / beta
+    if np.any(z <= 0):
+        return math.inf
+    return float(np.sum(np.log(beta) + (1.0 + 1.0 / xi) * np.log(z) + np.power(z, -1.0 / xi)))
+
+
+def fit_ml(tau):
+    """Maximum likelihood. The times are divided by their median first (the fit is then exactly
+    scale-equivariant) and the oracle's own negative log-likelihood is minimised by Nelder-Mead
+    from several starts -- scipy's GEV fit (shape c = -xi) and shapes xi = 0.2, 0.5, 1, 2 with
+    location and scale matching the sample median and interquartile range -- keeping the best."""
+    t0 = np.asarray(tau, dtype=np.float64)
+    sc = float(np.median(t0))
+    t = t0 / sc
+    obj = lambda v: nll((v[0], math.exp(v[1]), math.exp(v[2])), t)
+    starts = []
+    c, loc, scale = stats.genextreme.fit(t)
+    starts.append((loc, scale, max(-c, 1e-3)))
+    q1, q2, q3 = np.quantile(t, [0.25, 0.5, 0.75])
+    for xi in (0.2, 0.5, 1.0, 2.0):
+        # Eq. (9) inverted at p = 1/4, 1/2, 3/4 for this xi: the spread fixes beta, the median mu
+        g = lambda p: ((-math.log(p)) ** (-xi) - 1.0) / xi
+        beta = (q3 - q1) / (g(0.75) - g(0.25))
+        starts.append((q2 - beta * g(0.5), beta, xi))
+    opts = {"xatol": 1e-12, "fatol": 1e-13, "maxiter": 40000, "maxfev": 80000}
+    best = None
+    for mu, beta, xi in starts:
+        low = mu - beta / xi
+        if low >= t.min():
+            mu -= (low - t.min()) + 1e-3 * beta
+        r = optimize.minimize(obj, [mu, math.log(beta), math.log(xi)], method="Nelder-Mead", options=opts)
+        for _ in range(5):   # restart from the optimum until it no longer improves
+            r2 = optimize.minimize(obj, r.x, method="Nelder-Mead", options=opts)
+            if r2.fun >= r.fun - 1e-13 * abs(r.fun):
+                break
+            r = r2
+        if best is None or r.fun < best.fun:
+            best = r
+    v = best.x
+    # back to the original scale: mu and beta scale with the times, the likelihood gains n ln(sc)
+    return (float(v[0] * sc), float(math.exp(v[1]) * sc), float(math.exp(v[2]))), float(best.fun + len(t) * math.log(sc))
+
+
+def fit_ls(tau):
+    """Least squares between Eq. (9) and the plotting positions (i - 1/2)/n of the sorted sample."""
+    t = np.sort(np.asarray(tau, dtype=np.float64))
+    n = len(t)
+    pos = (np.arange(n) + 0.5) / n
+    (mu0, beta0, xi0), _ = fit_ml(t)
+    res = lambda v: cdf((v[0], math.exp(v[1]), math.exp(v[2])), t) - pos
+    r = optimize.least_squares(res, [mu0, math.log(beta0), math.log(xi0)], xtol=1e-15, ftol=1e-15, gtol=1e-15,
+                               max_nfev=20000)
+    v = r.x
+    return (float(v[0]), float(math.exp(v[1])), float(math.exp(v[2]))), float(np.sum(r.fun ** 2))
+
+
+def relative_performance(tau_m, tau_ref, eps=1e-4, method=0, blocks=0):
+    """r_pop = ratio of population means, r_eps = ratio of fitted quantile means (Table I), each
+    with the jackknife error over `blocks` contiguous blocks of realizations left out in turn
+    (0: one realization per block): err^2 = (B-1)/B sum_b (r_b - mean_b r_b)^2."""
+    a = np.asarray(tau_m, dtype=np.float64)
+    b = np.asarray(tau_ref, dtype=np.float64)
+    n = len(a)
+    B = n if blocks == 0 else blocks
+    fit = fit_ml if method == 0 else fit_ls
+
+    def est(keep):
+        pa, _ = fit(a[keep])
+        pb, _ = fit(b[keep])
+        return a[keep].mean() / b[keep].mean(), quantile_mean(pa, eps) / quantile_mean(pb, eps), pa, pb
+
+    rp, re, pa, pb = est(np.ones(n, bool))
+    jp, je = [], []
+    for k in range(B):
+        keep = np.ones(n, bool)
+        keep[k * n // B:(k + 1) * n // B] = False
+        x, y, _, _ = est(keep)
+        jp.append(x)
+        je.append(y)
+
+    def err(v):
+        v = np.asarray(v)
+        return math.sqrt((B - 1) / B * float(np.sum((v - v.mean()) ** 2)))
+    return {"r_pop": rp, "r_pop_err": err(jp), "r_eps": re, "r_eps_err": err(je), "fit_m": pa, "fit_ref": pb,
+            "blocks": B}

@@ -46,6 +46,21 @@ PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
 TUNING_FIELDS = ("speculate", "sweeps_per_launch", "schedule", "waves_per_cu", "hist")
 TUNE_RESULT_DTYPE = np.dtype([("tuning", np.int32, (5,)), ("attempts_per_s", np.float64)], align=True)
 
+class Frechet(C.Structure):
+    """nfm_frechet: parameters (mu, beta, xi) of Eq. (9)."""
+    _fields_ = [("mu", C.c_double), ("beta", C.c_double), ("xi", C.c_double)]
+
+    def as_tuple(self):
+        return (self.mu, self.beta, self.xi)
+
+
+class Ratio(C.Structure):
+    """nfm_ratio: relative performance with jackknife errors and the two fits."""
+    _fields_ = [("r_pop", C.c_double), ("r_pop_err", C.c_double), ("r_eps", C.c_double),
+                ("r_eps_err", C.c_double), ("fit_m", Frechet), ("fit_ref", Frechet),
+                ("blocks", C.c_int32), ("pad", C.c_int32)]
+
+
 _lib = None
 
 
@@ -115,6 +130,17 @@ def lib():
         "nfm_rec_targets": (i32, [vp, vp, vp]),
         "nfm_features": (i32, [vp, vp]),
     }
+    dbl = C.c_double
+    sig.update({
+        "nfm_frechet_cdf": (dbl, [C.POINTER(Frechet), dbl]),
+        "nfm_frechet_quantile": (dbl, [C.POINTER(Frechet), dbl]),
+        "nfm_frechet_mean": (dbl, [C.POINTER(Frechet)]),
+        "nfm_frechet_quantile_mean": (dbl, [C.POINTER(Frechet), dbl]),
+        "nfm_upper_gamma": (dbl, [dbl, dbl]),
+        "nfm_frechet_fit": (i32, [vp, i64, i32, C.POINTER(Frechet), C.POINTER(dbl)]),
+        "nfm_relative_performance": (i32, [vp, vp, i64, dbl, i32, i32, C.POINTER(Ratio)]),
+        "nfm_stats_last_error": (C.c_char_p, []),
+    })
     f32 = C.c_float
     sig.update({
         "nfm_mlp_n_params": (i32, []),
@@ -632,3 +658,65 @@ class Mlp:
             out = torch.empty((B, self.N_OUT), dtype=torch.float32, device=self.device)
         self._check(self._lib.nfm_mlp_infer_bf16(self.ctx, self._p(x), B, self._p(out)), "infer_bf16")
         return out
+
+
+# --------------------------------------------------------------------------- round-trip statistics
+# Host functions of the library (Sec. IV); times are per-realization mean round-trip times.
+
+def _frechet(params) -> Frechet:
+    mu, beta, xi = params
+    return Frechet(float(mu), float(beta), float(xi))
+
+
+def frechet_cdf(params, tau: float) -> float:
+    """F(tau) of Eq. (9) for params = (mu, beta, xi)."""
+    return lib().nfm_frechet_cdf(C.byref(_frechet(params)), float(tau))
+
+
+def frechet_quantile(params, p: float) -> float:
+    """Q(p) of Eq. (13)."""
+    return lib().nfm_frechet_quantile(C.byref(_frechet(params)), float(p))
+
+
+def frechet_mean(params) -> float:
+    """Eq. (11); inf for xi >= 1."""
+    return lib().nfm_frechet_mean(C.byref(_frechet(params)))
+
+
+def frechet_quantile_mean(params, eps: float) -> float:
+    """Eq. (14) in closed form."""
+    return lib().nfm_frechet_quantile_mean(C.byref(_frechet(params)), float(eps))
+
+
+def upper_gamma(a: float, x: float) -> float:
+    """Gamma(a, x) for real a, x > 0."""
+    return lib().nfm_upper_gamma(float(a), float(x))
+
+
+def _times(t) -> np.ndarray:
+    return np.ascontiguousarray(t, dtype=np.float64)
+
+
+def frechet_fit(tau, method: int = 0):
+    """Fit of Eq. (9) to times tau: method 0 maximum likelihood, 1 least squares on the
+    empirical CDF. Returns ((mu, beta, xi), objective)."""
+    t = _times(tau)
+    out, obj = Frechet(), C.c_double()
+    st = lib().nfm_frechet_fit(t.ctypes.data, len(t), int(method), C.byref(out), C.byref(obj))
+    if st != 0:
+        raise NfmError(st, "frechet_fit: " + lib().nfm_stats_last_error().decode())
+    return out.as_tuple(), obj.value
+
+
+def relative_performance(tau_m, tau_ref, eps: float = 1e-4, method: int = 0, blocks: int = 0) -> dict:
+    """r_pop and r_eps (Table I) of method m against the reference, with jackknife errors."""
+    a, b = _times(tau_m), _times(tau_ref)
+    if len(a) != len(b):
+        raise ValueError("relative_performance: paired samples of equal length")
+    out = Ratio()
+    st = lib().nfm_relative_performance(a.ctypes.data, b.ctypes.data, len(a), float(eps), int(method),
+                                        int(blocks), C.byref(out))
+    if st != 0:
+        raise NfmError(st, "relative_performance: " + lib().nfm_stats_last_error().decode())
+    return {"r_pop": out.r_pop, "r_pop_err": out.r_pop_err, "r_eps": out.r_eps, "r_eps_err": out.r_eps_err,
+            "fit_m": out.fit_m.as_tuple(), "fit_ref": out.fit_ref.as_tuple(), "blocks": out.blocks}
