@@ -597,18 +597,31 @@ void orc_pt_metro_table(int32_t M, const double* T, uint32_t* thr) {
 }
 
 /* Exchange table: for the pair of slots (s, s+1) and d = (E_{s+1} - E_s)/4 >= 1 the
- * exchange is accepted with x = exp((1/T_{s+1} - 1/T_s) (4d)) (Eq. (8)); entry
- * [s][d-1] holds its threshold. Exchanges with d <= 0 always succeed. D is the
- * smallest d at which every pair's threshold is 0 (so that larger d may be clamped
- * to D), but at most d_cap. Returns D; thr may be NULL to query it.              */
+ * exchange is accepted with x = exp((1/T_{s+1} - 1/T_s) (4d)) (Eq. (8)), evaluated as
+ * q^d with q = exp(4 (1/T_{s+1} - 1/T_s)) raised to d by binary powering (one FP64
+ * product per bit of d and per squaring, lowest bit first), so that any machine that
+ * is given q reproduces every entry bit for bit; entry [s][d-1] holds its threshold.
+ * Exchanges with d <= 0 always succeed. D is the smallest d at which every pair's
+ * threshold is 0 (so that larger d may be clamped to D), but at most d_cap. Returns D;
+ * thr may be NULL to query it.                                                       */
+double orc_pow_bin(double q, int32_t d) {
+  double r = 1.0, b = q;
+  while (d > 0) {
+    if (d & 1) r = r * b;
+    b = b * b;
+    d >>= 1;
+  }
+  return r;
+}
+
+double orc_pt_swap_q(double T_lo, double T_hi) { return exp(4.0 * (1.0 / T_hi - 1.0 / T_lo)); }
+
 int32_t orc_pt_swap_table(int32_t M, const double* T, int32_t d_cap, uint32_t* thr) {
   int32_t D = d_cap;
   for (int32_t d = 1; d <= d_cap; ++d) {
     int32_t all_zero = 1;
-    for (int32_t s = 0; s + 1 < M; ++s) {
-      double db = 1.0 / T[s + 1] - 1.0 / T[s];
-      if (quantize(exp(db * (double)(4 * d))) != 0u) all_zero = 0;
-    }
+    for (int32_t s = 0; s + 1 < M; ++s)
+      if (quantize(orc_pow_bin(orc_pt_swap_q(T[s], T[s + 1]), d)) != 0u) all_zero = 0;
     if (all_zero) {
       D = d;
       break;
@@ -616,8 +629,8 @@ int32_t orc_pt_swap_table(int32_t M, const double* T, int32_t d_cap, uint32_t* t
   }
   if (thr) {
     for (int32_t s = 0; s + 1 < M; ++s) {
-      double db = 1.0 / T[s + 1] - 1.0 / T[s];
-      for (int32_t d = 1; d <= D; ++d) thr[s * D + (d - 1)] = quantize(exp(db * (double)(4 * d)));
+      double q = orc_pt_swap_q(T[s], T[s + 1]);
+      for (int32_t d = 1; d <= D; ++d) thr[s * D + (d - 1)] = quantize(orc_pow_bin(q, d));
     }
   }
   return D;
@@ -634,8 +647,8 @@ int32_t orc_pt_swap_table(int32_t M, const double* T, int32_t d_cap, uint32_t* t
  * (s >> 2, t, real_id, (set << 8) | TAG_SWAP) under the walker seed.               */
 int32_t orc_pt_sweeps(int32_t L, const int8_t* J, int32_t M, int8_t* S, orc_walker* w, int32_t* slot,
                       const uint32_t* metro, const uint32_t* swap, int32_t D, int32_t e_bot, int32_t e_top,
-                      uint64_t walker_seed, uint32_t real_id, uint32_t set, uint64_t t0, uint64_t n_sweeps,
-                      uint64_t* swap_acc, int32_t* trace, int32_t check_energy) {
+                      uint64_t walker_seed, uint32_t real_id, uint32_t set, uint32_t walker0, uint64_t t0,
+                      uint64_t n_sweeps, uint64_t* swap_acc, int32_t* trace, int32_t check_energy) {
   int32_t N = L * L * L;
   int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
   uint32_t* slot_ctr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
@@ -651,7 +664,7 @@ int32_t orc_pt_sweeps(int32_t L, const int8_t* J, int32_t M, int8_t* S, orc_walk
   for (uint64_t t = t0; t < t0 + n_sweeps; ++t) {
     for (int32_t c = 0; c < M; ++c) {
       int8_t* Sc = S + (size_t)c * (size_t)N;
-      uint32_t walker = set * (uint32_t)M + (uint32_t)c;
+      uint32_t walker = walker0 + (uint32_t)c;
       for (int32_t a = 0; a < N; ++a) {
         int32_t i = order[a];
         int32_t u = orc_unsatisfied(L, J, Sc, i);

@@ -113,9 +113,13 @@ void orc_hist_bins(int32_t K, int32_t e_base, int32_t N, const uint64_t* H, doub
 /* Parallel tempering, Sec. II, Eq. (8). Temperatures strictly increasing. */
 void orc_pt_metro_table(int32_t M, const double* T, uint32_t* thr /* M x 8 */);
 int32_t orc_pt_swap_table(int32_t M, const double* T, int32_t d_cap, uint32_t* thr /* (M-1) x D or NULL */);
+/* q^d by binary powering (lowest bit first); q of the pair (T_lo, T_hi) = exp(4 (1/T_hi - 1/T_lo)). */
+double orc_pow_bin(double q, int32_t d);
+double orc_pt_swap_q(double T_lo, double T_hi);
 int32_t orc_pt_sweeps(int32_t L, const int8_t* J, int32_t M, int8_t* S /* M x N */, orc_walker* w /* M */,
                       int32_t* slot /* M */, const uint32_t* metro, const uint32_t* swap, int32_t D,
                       int32_t e_bot, int32_t e_top, uint64_t walker_seed, uint32_t real_id, uint32_t set,
+                      uint32_t walker0 /* walker index of configuration 0 */,
                       uint64_t t0, uint64_t n_sweeps, uint64_t* swap_acc /* M-1 or NULL */,
                       int32_t* trace /* M x n_sweeps or NULL */, int32_t check_energy);
 

@@ -16,6 +16,8 @@ import os
 import subprocess
 from dataclasses import dataclass
 
+import math
+
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,6 +87,10 @@ def lib():
         L.orc_muca_sweeps.restype = i32
         L.orc_metropolis_accept.argtypes = [u32, u32]
         L.orc_metropolis_accept.restype = i32
+        L.orc_pow_bin.argtypes = [dbl, i32]
+        L.orc_pow_bin.restype = dbl
+        L.orc_pt_swap_q.argtypes = [dbl, dbl]
+        L.orc_pt_swap_q.restype = dbl
         L.orc_brute_dos.argtypes = [i32, P(np.int8), P(np.uint64)]
         L.orc_brute_dos.restype = i32
         L.orc_power_profile.argtypes = [dbl, dbl, dbl, dbl]
@@ -107,7 +113,7 @@ def lib():
         L.orc_pt_swap_table.argtypes = [i32, P(np.float64), i32, C.c_void_p]
         L.orc_pt_swap_table.restype = i32
         L.orc_pt_sweeps.argtypes = [i32, P(np.int8), i32, P(np.int8), C.c_void_p, P(np.int32), P(np.uint32),
-                                    P(np.uint32), i32, i32, i32, u64, u32, u32, u64, u64, C.c_void_p,
+                                    P(np.uint32), i32, i32, i32, u64, u32, u32, u32, u64, u64, C.c_void_p,
                                     C.c_void_p, i32]
         L.orc_pt_sweeps.restype = i32
         _lib = L
@@ -384,6 +390,69 @@ def production_weights(rz: Realization, st: RecursionState, kind: str, pl_dE=96.
 
 # --------------------------------------------------------------------------- parallel tempering
 
+# --------------------------------------------------------------------------- Wang-Landau (batched)
+
+def wl_k_top(eb: int) -> int:
+    """Lowest level with E >= 0: the estimate lives on [0, k_top]."""
+    return (-eb + 3) // 4
+
+
+@dataclass
+class WangLandau:
+    """Batched Wang-Landau state of one realization: ln g on [0, k_top] (zero elsewhere), the
+    histogram of the current stage, ln f, halvings so far, done flag, last flatness."""
+    lng: np.ndarray
+    hst: np.ndarray
+    ln_f: float
+    k_top: int
+    stage: int = 0
+    done: bool = False
+    flatness: float = 0.0
+    updates: int = 0
+
+
+def wl_init(K: int, eb: int, ln_f0: float) -> WangLandau:
+    return WangLandau(np.zeros(K), np.zeros(K, np.uint64), float(ln_f0), wl_k_top(eb))
+
+
+def wl_update(st: WangLandau, H, flat_tol: float, ln_f_final: float) -> None:
+    """One step: ln g(k) += ln f H(k) and Hs(k) += H(k) on k <= k_top; flatness = min/mean of Hs
+    over the levels it visited; a flat stage halves ln f and clears Hs; done once ln f < final."""
+    if st.done:
+        return
+    for k in range(st.k_top + 1):
+        h = int(H[k])
+        if h:
+            st.lng[k] += st.ln_f * float(h)
+        st.hst[k] += np.uint64(h)
+    vis = [int(x) for x in st.hst[:st.k_top + 1] if x > 0]
+    flat = (float(min(vis)) / (float(sum(vis)) / float(len(vis)))) if vis else 0.0
+    st.flatness = flat
+    st.updates += 1
+    if flat >= flat_tol:
+        st.ln_f = 0.5 * st.ln_f
+        st.stage += 1
+        st.hst[:] = 0
+        if st.ln_f < ln_f_final:
+            st.done = True
+
+
+def wl_thresholds(st: WangLandau, K: int):
+    """Tables of the weights lnW = -ln g on [0, k_top]."""
+    return build_thresholds(K, -st.lng[:st.k_top + 1], 0, st.k_top)
+
+
+def wl_to_rec_steps(st: WangLandau):
+    """(k_lo, b) handed to the recursion: visited = ln g > 0, k_lo = the lowest visited level,
+    b(k) = ln g(k+1) - ln g(k) on [k_lo, k_top), zero elsewhere."""
+    vis = [k for k in range(st.k_top + 1) if st.lng[k] > 0.0]
+    k_lo = min(vis) if vis else st.k_top
+    b = np.zeros(len(st.lng))
+    for k in range(k_lo, st.k_top):
+        b[k] = st.lng[k + 1] - st.lng[k]
+    return k_lo, b
+
+
 def pt_temperatures(M: int, t_min: float = 0.2, t_max: float = 2.0) -> np.ndarray:
     """Geometric temperature ladder T_s = t_min (t_max/t_min)^(s/(M-1))."""
     return np.array([t_min * (t_max / t_min) ** (s / (M - 1)) for s in range(M)], np.float64)
@@ -394,6 +463,14 @@ def pt_metro_table(T) -> np.ndarray:
     thr = np.zeros(len(T) * 8, np.uint32)
     lib().orc_pt_metro_table(len(T), T, thr)
     return thr.reshape(len(T), 8)
+
+
+def pow_bin(q: float, d: int) -> float:
+    return lib().orc_pow_bin(float(q), int(d))
+
+
+def pt_swap_q(T_lo: float, T_hi: float) -> float:
+    return lib().orc_pt_swap_q(float(T_lo), float(T_hi))
 
 
 def pt_swap_table(T, d_cap: int) -> np.ndarray:
@@ -413,20 +490,63 @@ class PTSet:
     real_id: int
     walker_seed: int
     set_index: int
+    walker0: int           # walker index of configuration 0
     S: np.ndarray          # int8 [M, N]
     w: np.ndarray          # WALKER_DTYPE [M]
     slot: np.ndarray       # int32 [M], temperature slot of each configuration
     t: int = 0
 
 
+def pt_set_walker0(M, set_index):
+    """Walker index of configuration 0 of a set: every group of 64 walkers holds floor(64/M)
+    sets of M consecutive walkers (the rest of the group idles)."""
+    spw = 64 // M
+    return 64 * (set_index // spw) + M * (set_index % spw)
+
+
 def make_pt_set(L, disorder_seed, real_id, walker_seed, M, set_index=0) -> PTSet:
-    """Configurations start from the spins of walkers set*M .. set*M+M-1; configuration c
-    starts at slot c."""
+    """Configurations start from the spins of the set's walkers walker0 .. walker0+M-1;
+    configuration c starts at slot c."""
     J = couplings(L, disorder_seed, real_id)
-    ws = [set_index * M + c for c in range(M)]
+    w0 = pt_set_walker0(M, set_index)
+    ws = [w0 + c for c in range(M)]
     S = np.stack([spins(L, walker_seed, real_id, w) for w in ws])
     E0 = np.array([energy(L, J, S[c]) for c in range(M)], np.int32)
-    return PTSet(L, J, real_id, walker_seed, set_index, S, new_walkers(M, E0), np.arange(M, dtype=np.int32))
+    return PTSet(L, J, real_id, walker_seed, set_index, w0, S, new_walkers(M, E0), np.arange(M, dtype=np.int32))
+
+
+def pt_exchange_rates(acc_sets, t0, t1, M):
+    """Acceptance rate of each pair (s, s+1) of a realization from the accepted exchanges of its
+    sets ([n_sets, M-1]) over sweeps t0 <= t < t1: pair s is attempted once per set on every sweep
+    with t = s (mod 2)."""
+    acc = np.asarray(acc_sets, dtype=np.float64)
+    n_sets = acc.shape[0]
+    rates = np.zeros(M - 1)
+    for s in range(M - 1):
+        attempts = sum(1 for t in range(t0, t1) if t % 2 == s % 2)
+        rates[s] = acc[:, s].sum() / (n_sets * attempts)
+    return rates
+
+
+def pt_adapt_step(T, rates):
+    """One step of the temperature adaptation toward a constant exchange rate (a reading of the
+    protocol the paper adopts, whose update it does not print): with gaps g_s = 1/T_s - 1/T_{s+1},
+    g_s <- g_s (-ln A_s)^(-1/4) (A_s clamped to [1e-6, 1 - 1e-12]), then all gaps rescaled to their
+    old sum so that T_0 and T_{M-1} stay."""
+    beta = [1.0 / float(x) for x in T]
+    M = len(beta)
+    span = beta[0] - beta[M - 1]
+    gaps, total = [], 0.0
+    for s in range(M - 1):
+        a = min(max(float(rates[s]), 1e-6), 1.0 - 1e-12)
+        g = (beta[s] - beta[s + 1]) * (-math.log(a)) ** -0.25
+        gaps.append(g)
+        total += g
+    new = list(beta)
+    for s in range(M - 2):
+        new[s + 1] = new[s] - gaps[s] * (span / total)
+    new[M - 1] = beta[M - 1]
+    return np.array([1.0 / b for b in new])
 
 
 def pt_sweeps(ps: PTSet, metro, swap, e_bot, e_top, n_sweeps, swap_acc=None, trace=False, check_energy=False):
@@ -438,7 +558,7 @@ def pt_sweeps(ps: PTSet, metro, swap, e_bot, e_top, n_sweeps, swap_acc=None, tra
     tr = np.zeros((M, n_sweeps), np.int32) if trace else None
     S = np.ascontiguousarray(ps.S)
     rc = lib().orc_pt_sweeps(ps.L, ps.J, M, S, ps.w.ctypes.data, ps.slot, metro, swap.reshape(-1), D,
-                             e_bot, e_top, ps.walker_seed, ps.real_id, ps.set_index, ps.t, n_sweeps,
+                             e_bot, e_top, ps.walker_seed, ps.real_id, ps.set_index, ps.walker0, ps.t, n_sweeps,
                              None if swap_acc is None else swap_acc.ctypes.data,
                              None if tr is None else tr.ctypes.data, 1 if check_energy else 0)
     if rc == -1:

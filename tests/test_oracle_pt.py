@@ -159,3 +159,65 @@ def test_rt_tau_hand_example(orc):
     tau, trips, cens = orc.rt_tau(w["rt_count"], w["t_first"], w["t_last"], N, min_trips=4)
     assert cens and math.isnan(tau)
     assert orc.rt_population([1.0, float("nan"), 3.0]) == 2.0
+
+
+# ----------------------------------------------------------------------------- temperature adaptation
+
+def test_pt_set_walkers_fill_groups_of_64(orc):
+    # floor(64/M) sets per group of 64 walkers, the rest of the group idle
+    assert [orc.pt_set_walker0(7, g) for g in range(11)] == [0, 7, 14, 21, 28, 35, 42, 49, 56, 64, 71]
+    assert [orc.pt_set_walker0(20, g) for g in range(5)] == [0, 20, 40, 64, 84]
+    assert [orc.pt_set_walker0(32, g) for g in range(4)] == [0, 32, 64, 96]
+
+
+def test_exchange_rates_count_attempts_by_parity(orc):
+    acc = np.array([[3, 4, 5], [1, 2, 3]])
+    # sweeps 5..10: t = 5, 7, 9 attempt odd pairs (s = 1), t = 6, 8, 10 even ones (s = 0, 2)
+    r = orc.pt_exchange_rates(acc, 5, 11, 4)
+    assert np.allclose(r, [4 / 6, 6 / 6, 8 / 6])
+    r = orc.pt_exchange_rates(acc, 5, 10, 4)   # t = 6, 8 even; 5, 7, 9 odd
+    assert np.allclose(r, [4 / 4, 6 / 6, 8 / 4])
+
+
+def test_adapt_step_fixed_point_and_ends(orc):
+    T = orc.pt_temperatures(9, 0.2, 3.2)
+    same = orc.pt_adapt_step(T, np.full(8, 0.37))
+    assert np.allclose(same, T, rtol=1e-14, atol=0)
+    new = orc.pt_adapt_step(T, np.array([0.5, 0.5, 0.1, 0.5, 0.5, 0.5, 0.9, 0.5]))
+    assert new[0] == T[0] and new[-1] == pytest.approx(T[-1], rel=1e-15)
+    assert np.all(np.diff(new) > 0)
+    g_old, g_new = np.diff(1 / T), np.diff(1 / new)
+    # the pair with the fewest exchanges gets a narrower gap, the one with the most a wider one
+    ratio = g_new / g_old
+    assert ratio[2] < ratio[0] < ratio[6]
+
+
+def test_adapt_converges_to_equal_rates_on_a_gaussian_model(orc):
+    # overlapping Gaussian energy distributions: A_s = exp(-c_s gap_s^2), c_s growing toward low T
+    M = 12
+    T = orc.pt_temperatures(M, 0.2, 3.2)
+    c = np.linspace(10.0, 1.0, M - 1)
+    for _ in range(80):
+        gaps = np.diff(-1.0 / T)          # beta_s - beta_{s+1} > 0
+        T = orc.pt_adapt_step(T, np.exp(-c * gaps ** 2))
+    A = np.exp(-c * np.diff(-1.0 / T) ** 2)
+    assert A.max() - A.min() < 1e-6 * A.mean()
+    assert T[0] == pytest.approx(0.2, rel=1e-14) and T[-1] == pytest.approx(3.2, rel=1e-12)
+
+
+def test_swap_probability_by_binary_powering(orc):
+    """q^d by binary powering equals exp(d ln q) to rounding, and exp(4 d (1/T_hi - 1/T_lo))
+    (Eq. (8)) to a few units in the last place; the table quantizes exactly these values."""
+    import math
+    T = orc.pt_temperatures(8, 0.2, 3.2)
+    q = orc.pt_swap_q(T[2], T[3])
+    assert q == math.exp(4.0 * (1.0 / T[3] - 1.0 / T[2]))
+    for d in (1, 2, 3, 7, 64, 100, 1023):
+        assert orc.pow_bin(q, d) == pytest.approx(math.exp(4.0 * d * (1.0 / T[3] - 1.0 / T[2])), rel=1e-13)
+    r = 1.0
+    for d in range(1, 40):          # repeated products agree with the powering to rounding
+        r *= q
+        assert orc.pow_bin(q, d) == pytest.approx(r, rel=1e-14)
+    tab = orc.pt_swap_table(T, 200)
+    assert tab[2, 6] == math.floor(math.ldexp(orc.pow_bin(q, 7), 32))
+    assert np.all(np.diff(tab.astype(np.int64), axis=1) <= 0)
