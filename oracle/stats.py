@@ -2,7 +2,7 @@
 
 Written from the definitions: the Frechet CDF of Eq. (9), its density, the distribution mean of
 Eq. (10) and the quantile mean of Eq. (14) as the integrals they are defined by (mpmath
-quadrature), the quantile function of Eq. (13) as the inverse of Eq. (9), maximum-likelihood and
+quadrature, in the variable p = F(tau)), the quantile function of Eq. (13) as the inverse of Eq. (9), maximum-likelihood and
 least-squares fits as the optima of their objectives (scipy's optimizers as steps), and the
 relative performance r of Table I with a delete-a-block jackknife (the paper names the jackknife
 without its variant). Only the tests and the CPU leg of the benchmark use this module.
@@ -66,28 +66,35 @@ def _mp_pdf(params):
 
 
 def quantile_mean(params, eps, dps=30):
-    """Eq. (14): the integral of tau f(tau) from the lower end of the support to Q(1 - eps), by
-    quadrature over log-spaced pieces (eps = 0: the distribution mean of Eq. (10), inf for xi >= 1)."""
+    """Eq. (14): the integral of tau f(tau) from the lower end of the support to Q(1 - eps)
+    (eps = 0: the distribution mean of Eq. (10), inf for xi >= 1), taken in the variable p = F(tau)
+    as the integral of Q(p) over [0, 1 - eps] -- the same integral after the substitution, with Q
+    the algebraic inverse of Eq. (9), mu + beta (z - 1)/xi, z = (-ln p)^(-xi) -- by quadrature
+    in s = -ln(1 - p), with breakpoints every ln 10 in s. In p the integrand stays bounded in size for any xi > 0
+    (in tau the density's exponent 1/xi overflows as xi -> 0, the Gumbel limit)."""
     mu, beta, xi = params
     if eps == 0.0 and xi >= 1.0:
         return math.inf
     with mpmath.workdps(dps):
-        f = _mp_pdf(params)
-        lo = mpmath.mpf(support_lower(mu, beta, xi))
         mu_m, beta_m, xi_m = (mpmath.mpf(v) for v in params)
-        if eps == 0.0:
-            hi = mpmath.inf
-        else:
-            hi = mu_m + beta_m / xi_m * ((-mpmath.log(1 - mpmath.mpf(eps))) ** (-xi_m) - 1)
-        # breakpoints: the bulk near the mode, then geometric steps through the tail
-        pts = [lo, lo + beta_m * mpmath.mpf("0.01"), lo + beta_m * mpmath.mpf("0.1"), lo + beta_m]
-        step = beta_m
-        while pts[-1] + step < (hi if hi != mpmath.inf else lo + beta_m * mpmath.mpf(10) ** 80):
-            step *= 4
-            pts.append(pts[-1] + step)
-        pts.append(hi)
-        val = mpmath.quad(lambda t: t * f(t), pts)
-        return float(val)
+
+        def integrand(s):
+            # u = 1 - p = e^-s, so dp = -e^-s ds; -ln p stays accurate at both ends, and
+            # (z - 1)/xi with z = exp(-xi ln(-ln p)) is formed without cancellation for small xi
+            if s <= 0:
+                return mpmath.mpf(0)
+            ln_p = mpmath.log(-mpmath.expm1(-s)) if s < 1 else mpmath.log1p(-mpmath.exp(-s))
+            Qp = mu_m + beta_m * mpmath.expm1(-xi_m * mpmath.log(-ln_p)) / xi_m
+            return Qp * mpmath.exp(-s)
+        # s over [0, -ln eps] (to infinity for eps = 0), with breakpoints every ln 10
+        top = mpmath.inf if eps == 0.0 else -mpmath.log(mpmath.mpf(eps))
+        pts = [mpmath.mpf(0), mpmath.log(2)]
+        k = 1
+        while k * mpmath.log(10) < top and k <= 200:
+            pts.append(k * mpmath.log(10))
+            k += 1
+        pts.append(top)
+        return float(mpmath.quad(integrand, pts))
 
 
 def nll(params, tau):

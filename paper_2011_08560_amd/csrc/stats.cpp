@@ -261,9 +261,60 @@ bool valid_sample(const double* t, int64_t n) {
   return true;
 }
 
+// Nodes and weights of the 20-point Gauss-Legendre rule on [-1, 1] (Newton on P_20 from the
+// Chebyshev-like first guesses, the textbook construction).
+struct GaussLegendre20 {
+  double x[20], w[20];
+  GaussLegendre20() {
+    const int n = 20;
+    for (int i = 0; i < n; ++i) {
+      double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;   // P_0, P_1, then up the three-term recurrence to P_n
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        const double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-16) break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+};
+
+// (Gamma(1 - xi, x) - Gamma(1, x)) / xi = int_x^inf (t^-xi - 1)/xi e^-t dt, for small xi, where the
+// difference of the two gamma values cancels: in v = ln t the integrand expm1(-xi v)/xi exp(v - e^v)
+// is smooth and below 1e-18 outside [-45, 4]; composite 20-point Gauss-Legendre on panels of 1/2.
+double gamma_order_slope(double xi, double x) {
+  static const GaussLegendre20 gl;
+  const double v0 = x > 0.0 ? std::max(std::log(x), -45.0) : -45.0, v1 = 4.0;
+  if (v0 >= v1) return 0.0;
+  const int panels = std::max(1, (int)std::ceil((v1 - v0) / 0.5));
+  const double h = (v1 - v0) / panels;
+  double sum = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double c = v0 + (p + 0.5) * h;
+    double part = 0.0;
+    for (int i = 0; i < 20; ++i) {
+      const double v = c + 0.5 * h * gl.x[i];
+      part += gl.w[i] * std::expm1(-xi * v) / xi * std::exp(v - std::exp(v));
+    }
+    sum += 0.5 * h * part;
+  }
+  return sum;
+}
+
 double quantile_mean(const Params& d, double eps) {
-  if (eps <= 0.0) return d.xi < 1.0 ? d.mu + d.beta / d.xi * (std::tgamma(1.0 - d.xi) - 1.0) : kInf;
-  const double x = -std::log1p(-eps);
+  if (eps <= 0.0 && d.xi >= 1.0) return kInf;
+  const double x = eps > 0.0 ? -std::log1p(-eps) : 0.0;
+  // (1 - eps) = e^-x = Gamma(1, x): mu (1 - eps) + beta/xi (Gamma(1 - xi, x) - Gamma(1, x))
+  if (d.xi < 1e-2) return d.mu * (1.0 - eps) + d.beta * gamma_order_slope(d.xi, x);
+  if (eps <= 0.0) return d.mu + d.beta / d.xi * (std::tgamma(1.0 - d.xi) - 1.0);
   return (d.mu - d.beta / d.xi) * (1.0 - eps) + d.beta / d.xi * nfm_upper_gamma(1.0 - d.xi, x);
 }
 

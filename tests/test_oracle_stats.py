@@ -126,3 +126,13 @@ def test_relative_performance_of_scaled_times():
     other = _gev((200.0, 60.0, 0.5)).rvs(size=24, random_state=rng)
     r2 = S.relative_performance(other, ref, eps=1e-4, method=0, blocks=6)
     assert r2["r_pop_err"] > 1e-3
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4, 0.3])
+def test_quantile_mean_gumbel_limit(eps):
+    # xi -> 0 is the Gumbel law: the quantile mean tends to the Gumbel one (scipy's quadrature
+    # of x f(x) up to the Gumbel quantile, unnormalized; at eps = 0 the mean mu + beta gamma)
+    mu, beta = 184.76, 35.5
+    g = sst.gumbel_r(loc=mu, scale=beta)
+    want = mu + beta * np.euler_gamma if eps == 0.0 else g.expect(lambda x: x, ub=g.ppf(1 - eps))
+    assert S.quantile_mean((mu, beta, 1e-10), eps) == pytest.approx(want, rel=1e-8)

@@ -104,3 +104,12 @@ def test_bad_input(nfm):
     with pytest.raises(nfm.NfmError):
         nfm.relative_performance(t, t, eps=1e-4, blocks=11)
     assert math.isnan(nfm.upper_gamma(1.0, 0.0)) and math.isnan(nfm.frechet_quantile_mean((1, 1, 0.5), 1.0))
+
+
+@pytest.mark.parametrize("xi", [9e-3, 1e-4, 1e-7, 1e-10])
+def test_quantile_mean_near_the_gumbel_limit(nfm, xi):
+    # fits of narrow round-trip-time distributions end near xi = 0, where beta/xi (Gamma(1 - xi, x)
+    # - (1 - eps)) cancels; the library then integrates the difference quotient directly
+    params = (184.76, 35.5, xi)
+    for eps in (0.0, 1e-4, 0.3, 0.9):
+        assert nfm.frechet_quantile_mean(params, eps) == pytest.approx(S.quantile_mean(params, eps), rel=1e-13)
