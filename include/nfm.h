@@ -33,7 +33,8 @@
  *   thresholds     a table row per level, 8 uint32 per row: entry u = 0..6 is the
  *                  acceptance threshold of a flip with u unsatisfied bonds
  *                  (Delta E = 12 - 4u); a move is accepted iff thr == 0xFFFFFFFF
- *                  or r < thr for the attempt's random word r. A compact table
+ *                  or r < max(thr, 1) for the attempt's random word r (the least
+ *                  probability of a move is 2^-32). A compact table
  *                  holds rows [row0, row0+rows); lookups clamp the level into it.
  *
  * Memory and streams: the caller owns all device memory. nfm_workspace_bytes()
@@ -240,6 +241,35 @@ nfm_status nfm_rec_set_state(nfm_ctx* ctx, int32_t r, const double* b, const dou
                              const double* lnP, const double* lnW, const uint8_t* visited,
                              const nfm_rec_info* info);
 
+/* Wang-Landau estimate of the density of states (named in Sec. II as an alternative estimator;
+ * its steps are not printed there), in batched form: the walkers of a realization share one
+ * estimate ln g on the levels [0, k_top] (k_top = lowest level with E >= 0; W constant above).
+ * nfm_wl_init: ln g = 0, ln f = ln_f0 > 0, stage histogram 0, weights lnW = -ln g = 0 and their
+ *   tables (rows from level 0 to k_top + 3); clears the histograms.
+ * A step: nfm_run_sweeps(n), then nfm_wl_update: every level k <= k_top gains
+ *   ln g(k) += ln f H(k) (H = the histogram since the last update, one entry per walker per
+ *   sweep), H is added to the stage histogram Hs and cleared; flatness = min/mean of Hs over the
+ *   levels it visited; if flatness >= flat_tol, ln f <- ln f / 2 (a new stage, Hs cleared) and the
+ *   realization is done once ln f < ln_f_final (later updates leave it unchanged). Then the next
+ *   weights and tables. host_info (may be NULL) receives every realization's nfm_wl_info.
+ * nfm_wl_get: realization r's ln g and stage histogram (3N/2+1 entries each; either may be NULL).
+ * nfm_wl_to_rec: hands the estimate to the recursion (nfm_rec_*): visited = levels with ln g > 0,
+ *   k_lo the lowest of them, b(k) = ln g(k+1) - ln g(k) on [k_lo, k_top), p = 0, the given
+ *   profile; weights, tables and round-trip bounds as after nfm_rec_update; clears the
+ *   histograms. The recursion can then refine it (nfm_rec_update) or produce (nfm_rec_production). */
+typedef struct {
+  double ln_f;       /* current modification factor */
+  double flatness;   /* last update */
+  int32_t stage;     /* halvings so far */
+  int32_t done;      /* ln f < ln_f_final */
+  int32_t k_top;
+  int32_t updates;
+} nfm_wl_info;
+nfm_status nfm_wl_init(nfm_ctx* ctx, double ln_f0);
+nfm_status nfm_wl_update(nfm_ctx* ctx, double flat_tol, double ln_f_final, nfm_wl_info* host_info);
+nfm_status nfm_wl_get(nfm_ctx* ctx, int32_t r, double* host_lng, uint64_t* host_hst, nfm_wl_info* info);
+nfm_status nfm_wl_to_rec(nfm_ctx* ctx, int32_t profile, double pl_dE, double pl_alpha);
+
 /* Launch tuning of nfm_run_sweeps (results do not depend on it: the random stream is indexed
  * by sweep, site and walker, and all accumulation is integer).
  *   speculate: -1 automatic (= off), 0 off, 1 on. With speculation each attempt also loads the
@@ -288,38 +318,60 @@ nfm_status nfm_autotune(nfm_ctx* ctx, int32_t calib_sweeps, const char* cache_pa
 nfm_status nfm_sync(nfm_ctx* ctx);
 
 /* ---------------------------------------------------------------------------------------
- * Parallel tempering (Sec. II, Eq. (8)), the baseline the paper compares against. The
- * walkers of each realization form walkers/M sets of M configurations (walker index
- * set*M + c); each configuration sits at one temperature slot of the set, slots being a
- * permutation of 0..M-1. One PT sweep: every configuration makes one checkerboard sweep of
- * canonical Metropolis attempts at its slot's temperature (random words as in
- * nfm_run_sweeps, tag 4 instead of 1); then its energy goes through the round-trip
- * bookkeeping (bounds of nfm_set_rt_bounds; stamp (t+1) N, so round-trip times come out in
- * PT sweeps) and the trace; then the slot pairs (s, s+1) with s = t (mod 2) try an
- * exchange with probability min(1, exp((1/T_{s+1} - 1/T_s)(E_{s+1} - E_s))), taking
+ * Parallel tempering (Sec. II, Eq. (8)), the baseline the paper compares against. Each group
+ * of 64 walkers of a realization (walkers 64q .. 64q + 63) holds floor(64/M) sets of M
+ * configurations: set g of the group is walkers 64q + gM + c, c = 0..M-1, with set index
+ * q floor(64/M) + g within the realization; the group's remaining walkers idle at slot 0 (they
+ * sweep at the lowest temperature and take part in no exchange and no round-trip bookkeeping).
+ * Each configuration sits at one temperature slot of its set, slots being a permutation of
+ * 0..M-1. Temperatures T_0 < ... < T_{M-1} are per realization. One PT sweep: every
+ * configuration makes one checkerboard sweep of canonical Metropolis attempts at its slot's
+ * temperature (random words as in nfm_run_sweeps, tag 4 instead of 1); then its energy goes
+ * through the round-trip bookkeeping (bounds of nfm_set_rt_bounds; stamp (t+1) N, so round-trip
+ * times come out in PT sweeps) and the trace; then the slot pairs (s, s+1) with s = t (mod 2)
+ * try an exchange with probability min(1, exp((1/T_{s+1} - 1/T_s)(E_{s+1} - E_s))), taking
  * output[s & 3] of Philox counter (s >> 2, t, real_id, (set << 8) | 5) under the walker seed.
+ * Thresholds, with beta = 1.0/T in FP64: Metropolis entry u of slot s, floor(exp(-beta_s 4m) 2^32)
+ * for m = 3 - u > 0 and 0xFFFFFFFF for m <= 0 (acceptance as in nfm_run_sweeps), computed on the
+ * host whenever temperatures change; exchange of slots (s, s+1) whose energies differ by 4d,
+ * d > 0: floor(q_s^d 2^32) (0xFFFFFFFF if q_s^d >= 1) with q_s = exp(4 (beta_{s+1} - beta_s))
+ * from the host and q_s^d formed on the device by binary powering (r = 1, b = q; per bit of d
+ * from the lowest: r *= b if set, then b *= b; FP64 products), accepted iff it is 0xFFFFFFFF or
+ * r < it. The power has no cap on d.
  * Energies are tracked per attempt, so nfm_compute_energies must have run first.
  *
- * nfm_pt_init: M a power of two in [2, 64]; host_temps[M] strictly increasing, > 0. Builds
- *   on the host (FP64) the Metropolis table (M rows x 8 words in the layout of the
- *   multicanonical tables: entry u = 0..6 is the threshold of the step m = 3 - u,
- *   floor(exp(-(1/T)(4m)) 2^32) for m > 0, 0xFFFFFFFF for m <= 0, entry 7 = 0) and the exchange
- *   table ((M-1) rows x D: entry [s][d-1] = floor(exp((1/T_{s+1} - 1/T_s)(4d)) 2^32), D the
- *   first d at which every row is 0, at most 3N/2 + 1; larger d clamp to D), puts walker
- *   set*M + c at slot c and clears the exchange counters. Round-trip state is left as is
- *   (see nfm_reset_round_trips). EINVAL on bad M or temperatures, ESTATE without couplings. */
+ * nfm_pt_init: M in [2, 64]; host_temps[M] strictly increasing, > 0, for every realization;
+ *   puts configuration c of every set at slot c (idle walkers at 0) and clears the exchange
+ *   counters. Round-trip state is left as is (see nfm_reset_round_trips). EINVAL on bad M or
+ *   temperatures, ESTATE without couplings.
+ * nfm_pt_set_temps / nfm_pt_get_temps: the M temperatures of realization r.
+ * nfm_pt_get_tables: the thresholds the kernel uses for realization r, for inspection: metro
+ *   [M][8] (u-order, entry 7 = 0), swap [M-1][D] for d = 1..D with D the first d at which every
+ *   pair's threshold is 0 (at most 3N/2 + 1 of the largest N); either array may be NULL.
+ * nfm_pt_adapt: one step of the per-realization temperature adaptation for a constant exchange
+ *   rate (the paper's protocol, Sec. II; its rule is not printed, this is a reading): from the
+ *   exchanges accepted since the last adapt (or init), the rate A_s of each pair of each
+ *   realization (over its sets and the sweeps that attempted the pair); host_rates (may be NULL)
+ *   receives them, [n_real][M-1], and *n_outside (may be NULL) the number outside
+ *   [rate_lo, rate_hi]. Then every gap beta_s - beta_{s+1} is multiplied by (-ln A_s)^(-1/4)
+ *   (A_s clamped to [1e-6, 1 - 1e-12]; half the step that equalises A = exp(-c gap^2)) and
+ *   the gaps are rescaled to their old sum, keeping T_0 and T_{M-1}; counters cleared.
+ *   ESTATE before two PT sweeps since the last clear. */
 nfm_status nfm_pt_init(nfm_ctx* ctx, int32_t M, const double* host_temps);
-/* Inject / read the tables (same layouts; D in [1, 3N/2 + 1] of the largest N). */
-nfm_status nfm_pt_set_tables(nfm_ctx* ctx, const uint32_t* host_metro, const uint32_t* host_swap, int32_t D);
-nfm_status nfm_pt_get_tables(nfm_ctx* ctx, uint32_t* host_metro, uint32_t* host_swap, int32_t* M, int32_t* D);
+nfm_status nfm_pt_set_temps(nfm_ctx* ctx, int32_t r, const double* host_temps);
+nfm_status nfm_pt_get_temps(nfm_ctx* ctx, int32_t r, double* host_temps);
+nfm_status nfm_pt_get_tables(nfm_ctx* ctx, int32_t r, uint32_t* host_metro, uint32_t* host_swap, int32_t* M,
+                             int32_t* D);
+nfm_status nfm_pt_adapt(nfm_ctx* ctx, double rate_lo, double rate_hi, double* host_rates, int32_t* n_outside);
 /* Run n PT sweeps of every walker (asynchronous on the stream; advances the sweep counter). */
 nfm_status nfm_pt_run_sweeps(nfm_ctx* ctx, uint64_t n_sweeps);
 /* Slots of all walkers (int32, nfm_n_walkers() entries); set_slots checks that each set holds a
- * permutation of 0..M-1. */
+ * permutation of 0..M-1 and that idle walkers are at slot 0. */
 nfm_status nfm_pt_read_slots(nfm_ctx* ctx, int32_t* host_slots);
 nfm_status nfm_pt_set_slots(nfm_ctx* ctx, const int32_t* host_slots);
-/* Accepted exchanges since nfm_pt_init: uint64 [n_walkers / M][M - 1], entry [g][s] for the
- * pair (s, s+1) of global set g = walker / M. */
+/* Accepted exchanges since nfm_pt_init or the last nfm_pt_adapt: uint64 [n_sets][M - 1], sets in
+ * walker order (realization by realization, set index within it), entry [g][s] for the pair
+ * (s, s+1). n_sets = (n_walkers / 64) floor(64/M). */
 nfm_status nfm_pt_read_exchanges(nfm_ctx* ctx, uint64_t* host_acc);
 
 /* ---------------------------------------------------------------------------------------
@@ -347,7 +399,8 @@ nfm_status nfm_rt_stats(nfm_ctx* ctx, int32_t r0, int32_t count, uint64_t min_tr
  *   nfm_frechet_mean: Eq. (11), mu + beta/xi (Gamma(1 - xi) - 1) for xi < 1, +inf otherwise.
  *   nfm_frechet_quantile_mean: Eq. (14), the mean integral cut at Q(1 - eps) and not renormalized,
  *     in closed form (mu - beta/xi)(1 - eps) + beta/xi Gamma(1 - xi, -ln(1 - eps)); eps in [0, 1)
- *     (eps = 0 gives Eq. (11)).
+ *     (eps = 0 gives Eq. (11)). For xi < 0.01, where the two terms cancel, the same value as
+ *     mu (1 - eps) + beta int_x^inf (t^-xi - 1)/xi e^-t dt, x = -ln(1 - eps) (quadrature).
  *   nfm_upper_gamma: the upper incomplete gamma function Gamma(a, x) for real a and x > 0 (NaN
  *     otherwise); for a <= 0 by Gamma(a, x) = (Gamma(a + 1, x) - x^a e^-x) / a from (0, 1], or
  *     from E1 = Gamma(0, x).

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnfm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "mlp_api.cpp", "stats.cpp", "lattice.hip", "tables.hip", "sweep.hip", "recursion.hip", "features.hip",
+SOURCES = ["api.cpp", "mlp_api.cpp", "stats.cpp", "lattice.hip", "tables.hip", "sweep.hip", "recursion.hip", "wl.hip", "features.hip",
            "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

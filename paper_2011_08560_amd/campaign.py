@@ -1,0 +1,290 @@
+"""Round-trip-time campaigns: the comparison of Sec. IV and the power-law parameter scan.
+
+For one lattice size, a batch of disorder realizations first runs the weight iteration (flat
+target) to convergence; the converged estimate S = ln Omega then gives the production ensembles
+of the methods compared in Table I -- flat (lnW = -S), 1/k (lnW = -ln sum_{E'<=E} Omega) and the
+power law (lnW = -S + ln P_SH, Eq. (5)) -- and parallel tempering runs on the same realizations.
+Each method runs until every realization has at least `min_trips` round trips between the lowest
+energy found and the top (E >= 0; for tempering the mean energy of the hottest slot), in chunks,
+realizations that are short of trips being run on ("requeued") up to a sweep cap, past which
+they count as censored. The per-realization mean round-trip times then go through the host
+statistics of the library: Frechet fits (Eq. (9)), shape xi, population and quantile means
+(Eq. (14)), and the ratios r of Table I against the power law with jackknife errors. Every
+simulation step runs in the library's kernels; this module only sequences calls.
+
+    python -m paper_2011_08560_amd.campaign --L 4 --real 512 --min-trips 100
+    python -m paper_2011_08560_amd.campaign --L 6 --real 256 --scan-dE 1 24 96 --scan-alpha -1 -2.4 -3.6
+    python -m paper_2011_08560_amd.campaign --L 6 --real 256 --estimators
+
+The second form is the scan of the power-law setting (Sec. II, Eq. (5)): the same realizations
+and converged estimates, one production run per (dE, alpha). The third compares the estimators of
+the density of states (the recursion of Sec. II and Wang-Landau) on sweeps to a flat histogram.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import nfm
+from .seeding import iterate, make_batch
+
+PT_TEMPS = [0.2 * 10.0 ** (m / 31.0) for m in range(32)]   # 32 temperatures geometric in [0.2, 2]
+PL_PAPER = (96.0, -3.6)                                      # the paper's setting of Eq. (5)
+METHODS = ("flat", "invk", "pl", "pt", "pt_adaptive")
+# the paper's tempering protocol: M replicas per L, T_max > 3, temperatures adapted per realization
+# for exchange rates in [0.4, 0.6]
+PAPER_M = {3: 7, 4: 7, 5: 12, 6: 14, 8: 20}
+ADAPT_T = (0.2, 3.2)
+
+
+def converge(b, sweeps, f_tol, n_max, log=None):
+    """Flat-target weight iteration until every realization converged once (or n_max rounds)."""
+    first = iterate(b, sweeps, f_tol, n_max, profile=(nfm.PROFILE_FLAT, 1.0, 0.0))
+    if log:
+        log(f"weight iteration: {int((first <= n_max).sum())}/{len(first)} converged, "
+            f"median round {float(np.median(first)):.0f}")
+    return first
+
+
+def run_until_trips(b, run, min_trips, chunk, cap, log=None, what=""):
+    """Run `run(chunk)` until every realization has min_trips round trips or `cap` sweeps have
+    run. Returns (tau per realization in sweeps, NaN = censored; sweeps run)."""
+    done = 0
+    while True:
+        run(chunk)
+        done += chunk
+        tau, summ = b.rt_stats(min_trips=min_trips)
+        if summ["n_censored"] == 0 or done >= cap:
+            break
+    if log:
+        log(f"{what}: {done} sweeps, {int(summ['n_used'])} realizations with >= {min_trips} trips, "
+            f"{int(summ['n_censored'])} censored")
+    return tau, done
+
+
+def production(b, method, min_trips, chunk, cap, pl=PL_PAPER, log=None):
+    """Round-trip times of one multicanonical production ensemble."""
+    prof = {"flat": (nfm.PROFILE_FLAT, 1.0, 0.0), "invk": (nfm.PROFILE_INVK, 1.0, 0.0),
+            "pl": (nfm.PROFILE_POWER, pl[0], pl[1])}[method]
+    b.rec_production(*prof)
+    b.reset_round_trips()
+    return run_until_trips(b, b.run_sweeps, min_trips, chunk, cap, log, method)
+
+
+def adapt_temperatures(b, M, rounds=40, sweeps=500, band=(0.4, 0.6), log=None):
+    """Equilibration with temperature adaptation per realization (nfm_pt_adapt) until every
+    pair's exchange rate lies in the band or `rounds` are spent. Returns (rounds, last rates)."""
+    rates = None
+    for it in range(1, rounds + 1):
+        b.pt_run_sweeps(sweeps)
+        rates, n_out = b.pt_adapt(M, *band)
+        if n_out == 0:
+            break
+    if log:
+        log(f"pt adaptation: {it} rounds of {sweeps} sweeps, rates in [{rates.min():.3f}, {rates.max():.3f}]")
+    return it, rates
+
+
+def tempering(b, L, min_trips, chunk, cap, burn=1000, adaptive=False, log=None):
+    """Round-trip times of parallel tempering (in PT sweeps) between each realization's lowest
+    energy found by the weight iteration and the mean energy of the hottest slot (averaged over
+    the batch after a burn-in). adaptive: the paper's protocol (M from PAPER_M, temperatures in
+    ADAPT_T adapted per realization) instead of the fixed 32-temperature ladder."""
+    info = b.rec_read_info()
+    b.compute_energies()
+    extra = {}
+    if adaptive:
+        M = PAPER_M.get(L, 20)
+        t0, t1 = ADAPT_T
+        b.pt_init([t0 * (t1 / t0) ** (s / (M - 1)) for s in range(M)])
+        rounds, rates = adapt_temperatures(b, M, log=log)
+        extra = {"M": M, "adapt_rounds": rounds, "rates_min": float(rates.min()), "rates_max": float(rates.max()),
+                 "rates_mean": float(rates.mean())}
+    else:
+        M = len(PT_TEMPS)
+        b.pt_init(PT_TEMPS)
+    b.pt_run_sweeps(burn)
+    ws = b.read_walkers()
+    slots = b.pt_slots()
+    e_hot = float(np.mean(ws["E"][slots == M - 1]))
+    e_top = int(math.floor(e_hot))
+    for r in range(b.n_real):
+        e_bot = b.e_base(r) + 4 * int(info["k_lo"][r])
+        b.set_rt_bounds(r, e_bot, max(e_top, e_bot + 4))
+    b.reset_round_trips()
+    tau, done = run_until_trips(b, b.pt_run_sweeps, min_trips, chunk, cap, log, "pt_adaptive" if adaptive else "pt")
+    return tau, done, e_top, extra
+
+
+def analyse(taus: dict, ref="pl", eps=1e-4, blocks=0):
+    """Fits and ratios over the realizations uncensored under every method (paired)."""
+    ok = np.ones(len(next(iter(taus.values()))), bool)
+    for t in taus.values():
+        ok &= np.isfinite(t) & (t > 0)
+    out = {"paired_realizations": int(ok.sum()), "eps": eps, "methods": {}}
+    for m, t in taus.items():
+        tt = t[ok]
+        rec = {"tau_pop": float(tt.mean()) if len(tt) else None}
+        if len(tt) >= 3:
+            fit, _ = nfm.frechet_fit(tt, 0)
+            rec.update({"frechet": {"mu": fit[0], "beta": fit[1], "xi": fit[2]},
+                        "quantile_mean": nfm.frechet_quantile_mean(fit, eps),
+                        "mean": nfm.frechet_mean(fit), "median": float(np.median(tt))})
+            if m != ref and ref in taus:
+                rec["r"] = nfm.relative_performance(tt, taus[ref][ok], eps=eps, method=0, blocks=blocks)
+                rec["r"].pop("fit_m")
+                rec["r"].pop("fit_ref")
+        out["methods"][m] = rec
+    return out
+
+
+def compare(L, n_real, methods=METHODS, min_trips=100, iter_sweeps=None, f_tol=0.5, n_max=60, chunk=None,
+            cap=None, first_id=0, eps=1e-4, blocks=0, log=None):
+    """The comparison of Sec. IV at one L; returns a JSON-able record."""
+    iter_sweeps = iter_sweeps or 1000 * L * L
+    chunk = chunk or 50 * L ** 3
+    cap = cap or 1000 * chunk
+    b = make_batch([L] * n_real, first_real_id=first_id)
+    first = converge(b, iter_sweeps, f_tol, n_max, log)
+    taus, cost = {}, {}
+    for m in methods:
+        if m.startswith("pt"):
+            continue
+        taus[m], cost[m] = production(b, m, min_trips, chunk, cap, log=log)
+    rec = {"L": L, "realizations": n_real, "min_trips": min_trips,
+           "weight_iteration": {"sweeps_per_round": iter_sweeps, "f_tol": f_tol, "n_max": n_max,
+                                "converged": int((first <= n_max).sum())}}
+    for m in ("pt", "pt_adaptive"):
+        if m in methods:
+            taus[m], cost[m], e_top, extra = tempering(b, L, min_trips, chunk, cap, adaptive=(m == "pt_adaptive"),
+                                                       log=log)
+            rec[m] = {"e_top": e_top, **extra}
+            if m == "pt":
+                rec[m]["temperatures"] = [PT_TEMPS[0], PT_TEMPS[-1], len(PT_TEMPS)]
+    b.close()
+    rec["sweeps_run"] = cost
+    rec["censored"] = {m: int((~np.isfinite(t)).sum()) for m, t in taus.items()}
+    rec["analysis"] = analyse(taus, eps=eps, blocks=blocks)
+    rec["tau"] = {m: [None if not np.isfinite(x) else float(x) for x in t] for m, t in taus.items()}
+    return rec
+
+
+def scan(L, n_real, dEs, alphas, min_trips=100, iter_sweeps=None, f_tol=0.5, n_max=60, chunk=None, cap=None,
+         first_id=0, log=None):
+    """Population mean round-trip time of the power-law ensemble over a (dE, alpha) grid."""
+    iter_sweeps = iter_sweeps or 1000 * L * L
+    chunk = chunk or 50 * L ** 3
+    cap = cap or 1000 * chunk
+    b = make_batch([L] * n_real, first_real_id=first_id)
+    converge(b, iter_sweeps, f_tol, n_max, log)
+    grid = []
+    for dE in dEs:
+        for a in alphas:
+            tau, done = production(b, "pl", min_trips, chunk, cap, pl=(dE, a), log=log)
+            ok = np.isfinite(tau)
+            grid.append({"dE": dE, "alpha": a, "tau_pop": float(tau[ok].mean()) if ok.any() else None,
+                         "median": float(np.median(tau[ok])) if ok.any() else None,
+                         "censored": int((~ok).sum()), "sweeps": done})
+    b.close()
+    return {"L": L, "realizations": n_real, "min_trips": min_trips, "grid": grid}
+
+
+def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0.8, wl_ln_f0=None, wl_final=None,
+               wl_max_steps=2000, first_id=0, log=None):
+    """Sweeps each estimator needs until its flat-target weights give a flat histogram (f_tol) on
+    the same realizations: the recursion from W = 1, and Wang-Landau (steps of wl_sweeps, ln f
+    from wl_ln_f0 halved at flatness wl_flat down to wl_final) handed to the recursion, which then
+    runs its rounds until the same convergence test passes. Rounds run 10 % extra thermalization
+    sweeps, counted. Returns a JSON-able record with per-realization totals.
+
+    The batched update adds ln f per counted visit but only after a whole step, so ln f0 is sized
+    to raise a level by about one per step at an even spread over the 3N/2 + 1 levels (a first
+    ln f of 1 per visit, as in one-walker Wang-Landau, lets ln g run far past its true range
+    between updates and the stages stall); wl_final defaults to six halvings below it."""
+    wl_sweeps = wl_sweeps or max(sweeps // 10, 1)
+    N = L ** 3
+    wl_ln_f0 = wl_ln_f0 or (3 * N // 2 + 1) / (64 * wl_sweeps)   # make_batch: 64 walkers each
+    wl_final = wl_final or wl_ln_f0 / 64
+    per_round = sweeps + int(round(0.1 * sweeps))
+    b = make_batch([L] * n_real, first_real_id=first_id)
+    first = iterate(b, sweeps, f_tol, n_max)
+    b.close()
+    plain = np.where(first <= n_max, first * per_round, np.nan).astype(float)
+    if log:
+        log(f"recursion: {int((first <= n_max).sum())}/{n_real} converged, median {np.nanmedian(plain):.0f} sweeps")
+    b = make_batch([L] * n_real, first_real_id=first_id)
+    b.wl_init(wl_ln_f0)
+    done_at = np.full(n_real, -1, np.int64)
+    for step in range(1, wl_max_steps + 1):
+        b.run_sweeps(wl_sweeps)
+        info = b.wl_update(wl_flat, wl_final)
+        newly = (info["done"] == 1) & (done_at < 0)
+        done_at[newly] = step
+        if (done_at > 0).all():
+            break
+    b.wl_to_rec()
+    after = iterate(b, sweeps, f_tol, n_max, initialized=True)
+    b.close()
+    wl_ok = (done_at > 0) & (after <= n_max)
+    wl_total = np.where(wl_ok, done_at * wl_sweeps + after * per_round, np.nan).astype(float)
+    if log:
+        log(f"wang-landau: {int((done_at > 0).sum())}/{n_real} reached ln f < {wl_final}, "
+            f"{int(wl_ok.sum())} converged after the hand-over, median {np.nanmedian(wl_total):.0f} sweeps")
+    both = np.isfinite(plain) & np.isfinite(wl_total)
+
+    def arm(x):
+        f = x[np.isfinite(x)]
+        return {"converged": int(len(f)), "median": float(np.median(f)) if len(f) else None,
+                "mean": float(f.mean()) if len(f) else None}
+    return {"L": L, "realizations": n_real, "sweeps_per_round": sweeps, "f_tol": f_tol, "n_max": n_max,
+            "wl": {"sweeps_per_step": wl_sweeps, "flat": wl_flat, "ln_f0": wl_ln_f0, "ln_f_final": wl_final,
+                   "median_stages_steps": float(np.median(done_at[done_at > 0])) if (done_at > 0).any() else None,
+                   "rounds_after_handover_median": float(np.median(after[after <= n_max])) if (after <= n_max).any() else None},
+            "recursion_sweeps": arm(plain), "wang_landau_sweeps": arm(wl_total),
+            "paired": int(both.sum()), "wl_fewer": int((wl_total[both] < plain[both]).sum()),
+            "wl_more": int((wl_total[both] > plain[both]).sum())}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--L", type=int, nargs="+", default=[4])
+    ap.add_argument("--real", type=int, default=256)
+    ap.add_argument("--methods", nargs="+", default=list(METHODS), choices=METHODS)
+    ap.add_argument("--min-trips", type=int, default=100)
+    ap.add_argument("--iter-sweeps", type=int, default=0)
+    ap.add_argument("--f-tol", type=float, default=0.5)
+    ap.add_argument("--n-max", type=int, default=60)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cap", type=int, default=0)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--first-id", type=int, default=0)
+    ap.add_argument("--scan-dE", type=float, nargs="*")
+    ap.add_argument("--scan-alpha", type=float, nargs="*")
+    ap.add_argument("--estimators", action="store_true",
+                    help="compare the recursion with Wang-Landau on sweeps to a flat histogram")
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
+    for L in args.L:
+        if args.estimators:
+            rec = estimators(L, args.real, args.iter_sweeps or 1000 * L * L, args.f_tol, args.n_max,
+                             first_id=args.first_id, log=log)
+        elif args.scan_dE and args.scan_alpha:
+            rec = scan(L, args.real, args.scan_dE, args.scan_alpha, args.min_trips, args.iter_sweeps or None,
+                       args.f_tol, args.n_max, args.chunk or None, args.cap or None, args.first_id, log)
+        else:
+            rec = compare(L, args.real, args.methods, args.min_trips, args.iter_sweeps or None, args.f_tol,
+                          args.n_max, args.chunk or None, args.cap or None, args.first_id, args.eps, args.blocks, log)
+            rec.pop("tau")
+        rec["wall_s"] = time.time() - t0
+        print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -29,7 +29,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t reals, waves, jabi, jk, spins, ws_i32, ws_u64, tables, hist, lnw, klo, ktop, trace, rstats, staging, total;
   size_t recs, rec_f64, rec_vis;
-  size_t pt_slot, pt_acc, pt_metro, pt_swap, rt_tau, rt_sum;
+  size_t pt_slot, pt_acc, pt_metro, pt_swap, pt_q, rt_tau, rt_sum, wl_f64, wl_hst, wl_info;
   size_t order, counter, snap_spins, snap_i32, snap_u64, snap_hist;
   int32_t pt_dcap;            // exchange-table width capacity: max over the batch of 3N/2 + 1
   int64_t total_walkers, total_waves, levels_total, jabi_words, jk_words, spin_words, table_words;
@@ -99,8 +99,12 @@ bool make_layout(const nfm_batch_desc* d, Layout* lay, std::string* why) {
   l.rec_vis = take((size_t)l.levels_total);
   l.pt_slot = take(4 * (size_t)l.total_walkers);
   l.pt_acc = take(8 * (size_t)l.total_walkers);
-  l.pt_metro = take(4 * 8 * (size_t)nfm::kMaxReplicas);
+  l.pt_metro = take(4 * 8 * (size_t)nfm::kMaxReplicas * (size_t)d->n_real);
   l.pt_swap = take(4 * (size_t)(nfm::kMaxReplicas - 1) * (size_t)l.pt_dcap);
+  l.pt_q = take(8 * (size_t)nfm::kMaxReplicas * (size_t)d->n_real);
+  l.wl_f64 = take(8 * 2 * (size_t)l.levels_total);
+  l.wl_hst = take(8 * (size_t)l.levels_total);
+  l.wl_info = take(sizeof(nfm::WlInfo) * (size_t)d->n_real);
   l.rt_tau = take(8 * (size_t)d->n_real);
   l.rt_sum = take(sizeof(nfm::RtSummaryDev));
   l.order = take(4 * (size_t)l.total_waves);
@@ -165,10 +169,19 @@ struct nfm_ctx {
     return a;
   }
   bool rec_ready = false;
-  int pt_M = 0, pt_D = 0;                  // parallel tempering: slots per set, exchange-table width
+  int pt_M = 0;                            // parallel tempering: slots per set
+  std::vector<double> pt_T;                // per realization kMaxReplicas temperatures (slot order)
+  uint64_t pt_t_reset = 0;                 // sweep counter when the exchange counters were cleared
   int32_t* d_pt_slot() { return (int32_t*)(ws + lay.pt_slot); }
   uint64_t* d_pt_acc() { return (uint64_t*)(ws + lay.pt_acc); }
   uint32_t* d_pt_metro() { return (uint32_t*)(ws + lay.pt_metro); }
+  double* d_pt_q() { return (double*)(ws + lay.pt_q); }
+  nfm::WlArrays wl_arrays() {
+    double* f = (double*)(ws + lay.wl_f64);
+    return nfm::WlArrays{f, (unsigned long long*)(ws + lay.wl_hst), f + lay.levels_total};
+  }
+  nfm::WlInfo* d_wl_info() { return (nfm::WlInfo*)(ws + lay.wl_info); }
+  bool wl_ready = false;
   uint32_t* d_pt_swap() { return (uint32_t*)(ws + lay.pt_swap); }
   nfm::WalkerState walker_state() {
     nfm::WalkerState s;
@@ -760,6 +773,65 @@ nfm_status nfm_rec_production(nfm_ctx* c, int32_t profile, double pl_dE, double 
   return pull_reals(c);
 }
 
+// ------------------------------------------------------------------------------------------
+// Wang-Landau estimate (batched form; see wl.hip).
+
+nfm_status nfm_wl_init(nfm_ctx* c, double ln_f0) {
+  NFM_GUARD(c);
+  if (!c->couplings) return fail(c, NFM_ESTATE, "wl_init: couplings not set");
+  if (!(ln_f0 > 0.0) || !std::isfinite(ln_f0)) return fail(c, NFM_EINVAL, "wl_init: ln_f0 must be positive and finite");
+  hipError_t e = nfm::launch_wl_init(c->d_reals(), c->n_real, c->wl_arrays(), c->d_wl_info(), ln_f0, c->d_tables(),
+                                     c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("wl_init: ") + hipGetErrorString(e));
+  NFM_HIP(c, hipMemsetAsync(c->d_hist(), 0, 8 * (size_t)c->lay.levels_total, c->stream));
+  c->wl_ready = true;
+  return pull_reals(c);
+}
+
+nfm_status nfm_wl_update(nfm_ctx* c, double flat_tol, double ln_f_final, nfm_wl_info* host_info) {
+  NFM_GUARD(c);
+  if (!c->wl_ready) return fail(c, NFM_ESTATE, "wl_update: call nfm_wl_init first");
+  if (!(flat_tol >= 0.0 && flat_tol <= 1.0) || !(ln_f_final > 0.0))
+    return fail(c, NFM_EINVAL, "wl_update: flat_tol in [0, 1] and ln_f_final > 0");
+  hipError_t e = nfm::launch_wl_update(c->d_reals(), c->n_real, c->wl_arrays(), c->d_wl_info(), c->d_hist(), flat_tol,
+                                       ln_f_final, c->d_tables(), c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("wl_update: ") + hipGetErrorString(e));
+  nfm_status st = pull_reals(c);
+  if (st != NFM_OK || !host_info) return st;
+  static_assert(sizeof(nfm_wl_info) == sizeof(nfm::WlInfo), "layout");
+  NFM_HIP(c, hipMemcpyAsync(host_info, c->d_wl_info(), sizeof(nfm_wl_info) * c->n_real, hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_wl_get(nfm_ctx* c, int32_t r, double* host_lng, uint64_t* host_hst, nfm_wl_info* info) {
+  NFM_GUARD(c);
+  if (!c->wl_ready) return fail(c, NFM_ESTATE, "wl_get: call nfm_wl_init first");
+  if (r < 0 || r >= c->n_real) return fail(c, NFM_EINVAL, "wl_get: bad realization");
+  const int64_t off = c->reals[r].level_off;
+  const size_t n = (size_t)nfm::level_capacity(c->reals[r].N);
+  nfm::WlArrays a = c->wl_arrays();
+  if (host_lng) NFM_HIP(c, hipMemcpyAsync(host_lng, a.lng + off, 8 * n, hipMemcpyDeviceToHost, c->stream));
+  if (host_hst) NFM_HIP(c, hipMemcpyAsync(host_hst, a.hst + off, 8 * n, hipMemcpyDeviceToHost, c->stream));
+  if (info) NFM_HIP(c, hipMemcpyAsync(info, c->d_wl_info() + r, sizeof(nfm_wl_info), hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_wl_to_rec(nfm_ctx* c, int32_t profile, double pl_dE, double pl_alpha) {
+  NFM_GUARD(c);
+  if (!c->wl_ready) return fail(c, NFM_ESTATE, "wl_to_rec: call nfm_wl_init first");
+  if (!valid_profile(profile, pl_dE, pl_alpha)) return fail(c, NFM_EINVAL, "wl_to_rec: bad profile");
+  hipError_t e = nfm::launch_wl_to_rec(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->wl_arrays(),
+                                       c->d_wl_info(), profile, pl_dE, pl_alpha, c->stream);
+  if (e == hipSuccess)
+    e = nfm::launch_rec_weights(c->d_reals(), c->d_recs(), c->n_real, c->rec_arrays(), c->d_tables(), 1, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("wl_to_rec: ") + hipGetErrorString(e));
+  NFM_HIP(c, hipMemsetAsync(c->d_hist(), 0, 8 * (size_t)c->lay.levels_total, c->stream));
+  c->rec_ready = true;
+  return pull_reals(c);
+}
+
 nfm_status nfm_rec_read_info(nfm_ctx* c, nfm_rec_info* host_info) {
   NFM_GUARD(c);
   if (!host_info) return fail(c, NFM_EINVAL, "rec_read_info: null pointer");
@@ -965,86 +1037,172 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
 // ------------------------------------------------------------------------------------------
 // Parallel tempering (Sec. II, Eq. (8)).
 
+static bool pt_valid_M(int M) { return M >= 2 && M <= nfm::kMaxReplicas; }
+
+static bool pt_valid_temps(int M, const double* T) {
+  if (!T) return false;
+  for (int s = 0; s < M; ++s)
+    if (!(T[s] > 0.0 && std::isfinite(T[s])) || (s > 0 && !(T[s] > T[s - 1]))) return false;
+  return true;
+}
+
+// Sets of the walkers (one wave = 64 walkers holds floor(64/M) sets of M lanes).
+static int64_t pt_sets_of(const nfm_ctx* c, int r) { return (int64_t)(c->reals[r].walkers / 64) * (64 / c->pt_M); }
+static int64_t pt_sets_total(const nfm_ctx* c) { return (c->lay.total_walkers / 64) * (64 / c->pt_M); }
+
 static uint32_t pt_quantize(double x) { return x >= 1.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(std::ldexp(x, 32)); }
 
-static bool pt_valid_M(int M) { return M >= 2 && M <= nfm::kMaxReplicas && (M & (M - 1)) == 0; }
+// Every realization's Metropolis rows (u-order, pad 0; step m = 3 - u, x = exp(-(1/T)(4m))) and
+// the q of each pair, exp(4 (1/T_{s+1} - 1/T_s)), from the host temperatures (FP64), uploaded.
+static nfm_status pt_upload(nfm_ctx* c) {
+  const int M = c->pt_M, R = c->n_real, X = nfm::kMaxReplicas;
+  std::vector<uint32_t> metro((size_t)R * X * 8, 0u);
+  std::vector<double> q((size_t)R * X, 0.0);
+  for (int r = 0; r < R; ++r) {
+    const double* T = &c->pt_T[(size_t)r * X];
+    for (int s = 0; s < M; ++s) {
+      const double beta = 1.0 / T[s];
+      for (int u = 0; u <= 6; ++u) {
+        const int m = 3 - u;
+        metro[((size_t)r * X + s) * 8 + u] = m <= 0 ? 0xFFFFFFFFu : pt_quantize(std::exp(-beta * (double)(4 * m)));
+      }
+      if (s + 1 < M) q[(size_t)r * X + s] = std::exp(4.0 * (1.0 / T[s + 1] - 1.0 / T[s]));
+    }
+  }
+  NFM_HIP(c, hipMemcpyAsync(c->d_pt_metro(), metro.data(), 4 * metro.size(), hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipMemcpyAsync(c->d_pt_q(), q.data(), 8 * q.size(), hipMemcpyHostToDevice, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
 
 nfm_status nfm_pt_init(nfm_ctx* c, int32_t M, const double* host_temps) {
   NFM_GUARD(c);
   if (!c->couplings) return fail(c, NFM_ESTATE, "pt_init: couplings not set");
-  if (!pt_valid_M(M)) return fail(c, NFM_EINVAL, "pt_init: M must be a power of two in [2, 64]");
-  if (!host_temps) return fail(c, NFM_EINVAL, "pt_init: null temperatures");
-  for (int s = 0; s < M; ++s)
-    if (!(host_temps[s] > 0.0 && std::isfinite(host_temps[s])) || (s > 0 && !(host_temps[s] > host_temps[s - 1])))
-      return fail(c, NFM_EINVAL, "pt_init: temperatures must be positive, finite and strictly increasing");
+  if (!pt_valid_M(M)) return fail(c, NFM_EINVAL, "pt_init: M must lie in [2, 64]");
+  if (!pt_valid_temps(M, host_temps))
+    return fail(c, NFM_EINVAL, "pt_init: temperatures must be positive, finite and strictly increasing");
   NFM_TRY(c, {
-    // Metropolis rows (u-order, pad 0): step m = 3 - u changes E by 4m, x = exp(-(1/T)(4m)).
-    std::vector<uint32_t> metro((size_t)M * 8, 0u);
-    for (int s = 0; s < M; ++s) {
-      const double beta = 1.0 / host_temps[s];
-      for (int u = 0; u <= 6; ++u) {
-        const int m = 3 - u;
-        metro[(size_t)s * 8 + u] = m <= 0 ? 0xFFFFFFFFu : pt_quantize(std::exp(-beta * (double)(4 * m)));
-      }
-    }
-    // Exchange rows: pair (s, s+1), d = (E_{s+1} - E_s)/4 >= 1, x = exp((1/T_{s+1} - 1/T_s)(4d));
-    // width D = first d at which every pair's threshold is 0 (larger d clamp to it exactly).
-    const int cap = c->lay.pt_dcap;
-    int D = cap;
-    for (int d = 1; d <= cap; ++d) {
-      bool zero = true;
-      for (int s = 0; s + 1 < M && zero; ++s) {
-        const double db = 1.0 / host_temps[s + 1] - 1.0 / host_temps[s];
-        if (pt_quantize(std::exp(db * (double)(4 * d))) != 0u) zero = false;
-      }
-      if (zero) {
-        D = d;
-        break;
-      }
-    }
-    std::vector<uint32_t> swap((size_t)(M - 1) * D);
-    for (int s = 0; s + 1 < M; ++s) {
-      const double db = 1.0 / host_temps[s + 1] - 1.0 / host_temps[s];
-      for (int d = 1; d <= D; ++d) swap[(size_t)s * D + (d - 1)] = pt_quantize(std::exp(db * (double)(4 * d)));
-    }
+    c->pt_T.assign((size_t)c->n_real * nfm::kMaxReplicas, 0.0);
+    for (int r = 0; r < c->n_real; ++r)
+      for (int s = 0; s < M; ++s) c->pt_T[(size_t)r * nfm::kMaxReplicas + s] = host_temps[s];
+    // configuration c of each set starts at slot c; idle lanes of a wave sit at slot 0
+    const int spw = 64 / M;
     std::vector<int32_t> slot(c->lay.total_walkers);
-    for (int64_t w = 0; w < c->lay.total_walkers; ++w) slot[w] = (int32_t)(w % M);  // walker offsets are multiples of 64
-    NFM_HIP(c, hipMemcpyAsync(c->d_pt_metro(), metro.data(), 4 * metro.size(), hipMemcpyHostToDevice, c->stream));
-    NFM_HIP(c, hipMemcpyAsync(c->d_pt_swap(), swap.data(), 4 * swap.size(), hipMemcpyHostToDevice, c->stream));
+    for (int64_t w = 0; w < c->lay.total_walkers; ++w) {   // walker offsets are multiples of 64
+      const int lane = (int)(w % 64);
+      slot[w] = lane < spw * M ? lane % M : 0;
+    }
+    c->pt_M = M;
+    nfm_status st = pt_upload(c);
+    if (st != NFM_OK) return st;
     NFM_HIP(c, hipMemcpyAsync(c->d_pt_slot(), slot.data(), 4 * slot.size(), hipMemcpyHostToDevice, c->stream));
     NFM_HIP(c, hipMemsetAsync(c->d_pt_acc(), 0, 8 * (size_t)c->lay.total_walkers, c->stream));
     NFM_HIP(c, hipStreamSynchronize(c->stream));
-    c->pt_M = M;
-    c->pt_D = D;
+    c->pt_t_reset = c->sweeps;
     return NFM_OK;
   })
 }
 
-nfm_status nfm_pt_set_tables(nfm_ctx* c, const uint32_t* host_metro, const uint32_t* host_swap, int32_t D) {
+nfm_status nfm_pt_set_temps(nfm_ctx* c, int32_t r, const double* host_temps) {
   NFM_GUARD(c);
-  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_set_tables: call nfm_pt_init first");
-  if (!host_metro || !host_swap || D < 1 || D > c->lay.pt_dcap)
-    return fail(c, NFM_EINVAL, "pt_set_tables: null pointer or D outside [1, 3N/2 + 1]");
-  NFM_HIP(c, hipMemcpyAsync(c->d_pt_metro(), host_metro, 4 * 8 * (size_t)c->pt_M, hipMemcpyHostToDevice, c->stream));
-  NFM_HIP(c, hipMemcpyAsync(c->d_pt_swap(), host_swap, 4 * (size_t)(c->pt_M - 1) * D, hipMemcpyHostToDevice, c->stream));
-  NFM_HIP(c, hipStreamSynchronize(c->stream));
-  c->pt_D = D;
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_set_temps: call nfm_pt_init first");
+  if (r < 0 || r >= c->n_real) return fail(c, NFM_EINVAL, "pt_set_temps: bad realization");
+  if (!pt_valid_temps(c->pt_M, host_temps))
+    return fail(c, NFM_EINVAL, "pt_set_temps: temperatures must be positive, finite and strictly increasing");
+  for (int s = 0; s < c->pt_M; ++s) c->pt_T[(size_t)r * nfm::kMaxReplicas + s] = host_temps[s];
+  NFM_TRY(c, { return pt_upload(c); })
+}
+
+nfm_status nfm_pt_get_temps(nfm_ctx* c, int32_t r, double* host_temps) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_get_temps: call nfm_pt_init first");
+  if (r < 0 || r >= c->n_real || !host_temps) return fail(c, NFM_EINVAL, "pt_get_temps: bad arguments");
+  for (int s = 0; s < c->pt_M; ++s) host_temps[s] = c->pt_T[(size_t)r * nfm::kMaxReplicas + s];
   return NFM_OK;
 }
 
-nfm_status nfm_pt_get_tables(nfm_ctx* c, uint32_t* host_metro, uint32_t* host_swap, int32_t* M, int32_t* D) {
+nfm_status nfm_pt_get_tables(nfm_ctx* c, int32_t r, uint32_t* host_metro, uint32_t* host_swap, int32_t* M, int32_t* D) {
   NFM_GUARD(c);
   if (!M || !D) return fail(c, NFM_EINVAL, "pt_get_tables: null pointer");
   *M = c->pt_M;
-  *D = c->pt_D;
+  *D = 0;
   if (c->pt_M == 0) return NFM_OK;
-  if (host_metro)
-    NFM_HIP(c, hipMemcpyAsync(host_metro, c->d_pt_metro(), 4 * 8 * (size_t)c->pt_M, hipMemcpyDeviceToHost, c->stream));
-  if (host_swap)
-    NFM_HIP(c, hipMemcpyAsync(host_swap, c->d_pt_swap(), 4 * (size_t)(c->pt_M - 1) * c->pt_D, hipMemcpyDeviceToHost,
-                              c->stream));
-  NFM_HIP(c, hipStreamSynchronize(c->stream));
-  return NFM_OK;
+  if (r < 0 || r >= c->n_real) return fail(c, NFM_EINVAL, "pt_get_tables: bad realization");
+  NFM_TRY(c, {
+    const int Mv = c->pt_M, cap = c->lay.pt_dcap;
+    hipError_t e = nfm::launch_pt_swap_table(c->d_pt_q(), r, Mv, cap, c->d_pt_swap(), c->stream);
+    if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("pt_swap_table: ") + hipGetErrorString(e));
+    std::vector<uint32_t> sw((size_t)(Mv - 1) * cap);
+    NFM_HIP(c, hipMemcpyAsync(sw.data(), c->d_pt_swap(), 4 * sw.size(), hipMemcpyDeviceToHost, c->stream));
+    if (host_metro)
+      NFM_HIP(c, hipMemcpyAsync(host_metro, c->d_pt_metro() + (size_t)r * nfm::kMaxReplicas * 8,
+                                4 * 8 * (size_t)Mv, hipMemcpyDeviceToHost, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    int Dv = cap;
+    for (int d = 1; d <= cap; ++d) {
+      bool zero = true;
+      for (int s = 0; s + 1 < Mv && zero; ++s) zero = sw[(size_t)s * cap + (d - 1)] == 0u;
+      if (zero) {
+        Dv = d;
+        break;
+      }
+    }
+    *D = Dv;
+    if (host_swap)
+      for (int s = 0; s + 1 < Mv; ++s)
+        for (int d = 1; d <= Dv; ++d) host_swap[(size_t)s * Dv + (d - 1)] = sw[(size_t)s * cap + (d - 1)];
+    return NFM_OK;
+  })
+}
+
+nfm_status nfm_pt_adapt(nfm_ctx* c, double rate_lo, double rate_hi, double* host_rates, int32_t* n_outside) {
+  NFM_GUARD(c);
+  if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_adapt: call nfm_pt_init first");
+  if (!(rate_lo >= 0.0) || !(rate_hi <= 1.0) || !(rate_lo <= rate_hi))
+    return fail(c, NFM_EINVAL, "pt_adapt: need 0 <= rate_lo <= rate_hi <= 1");
+  const uint64_t t0 = c->pt_t_reset, t1 = c->sweeps;
+  // sweeps t in [t0, t1) with t = s (mod 2): the exchange attempts of pair s per set
+  const uint64_t n_even = (t1 + 1) / 2 - (t0 + 1) / 2, n_odd = t1 / 2 - t0 / 2;
+  if (n_even == 0 || n_odd == 0) return fail(c, NFM_ESTATE, "pt_adapt: run at least two PT sweeps first");
+  NFM_TRY(c, {
+    const int M = c->pt_M;
+    std::vector<uint64_t> acc((size_t)pt_sets_total(c) * (M - 1));
+    NFM_HIP(c, hipMemcpyAsync(acc.data(), c->d_pt_acc(), 8 * acc.size(), hipMemcpyDeviceToHost, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    int outside = 0;
+    int64_t set0 = 0;
+    std::vector<double> beta(M), rate(M - 1), gap(M - 1);
+    for (int r = 0; r < c->n_real; ++r) {
+      const int64_t ns = pt_sets_of(c, r);
+      double* T = &c->pt_T[(size_t)r * nfm::kMaxReplicas];
+      for (int s = 0; s < M; ++s) beta[s] = 1.0 / T[s];
+      const double span = beta[0] - beta[M - 1];
+      double total = 0.0;
+      for (int s = 0; s + 1 < M; ++s) {
+        uint64_t a = 0;
+        for (int64_t g = 0; g < ns; ++g) a += acc[(size_t)(set0 + g) * (M - 1) + s];
+        rate[s] = (double)a / ((double)ns * (double)((s % 2 == 0) ? n_even : n_odd));
+        if (rate[s] < rate_lo || rate[s] > rate_hi) ++outside;
+        if (host_rates) host_rates[(size_t)r * (M - 1) + s] = rate[s];
+        // A = exp(-c gap^2) would be equalised by gap / sqrt(-ln A); half that step in log space
+        const double a_c = std::min(std::max(rate[s], 1e-6), 1.0 - 1e-12);
+        gap[s] = (beta[s] - beta[s + 1]) * std::pow(-std::log(a_c), -0.25);
+        total += gap[s];
+      }
+      const double bmax = beta[M - 1];
+      for (int s = 0; s + 2 < M; ++s) beta[s + 1] = beta[s] - gap[s] * (span / total);
+      beta[M - 1] = bmax;   // both ends stay where they are
+      for (int s = 0; s < M; ++s) T[s] = 1.0 / beta[s];
+      set0 += ns;
+    }
+    if (n_outside) *n_outside = outside;
+    nfm_status st = pt_upload(c);
+    if (st != NFM_OK) return st;
+    NFM_HIP(c, hipMemsetAsync(c->d_pt_acc(), 0, 8 * (size_t)c->lay.total_walkers, c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    c->pt_t_reset = c->sweeps;
+    return NFM_OK;
+  })
 }
 
 nfm_status nfm_pt_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
@@ -1070,11 +1228,12 @@ nfm_status nfm_pt_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
       a.n_sweeps = chunk;
       a.walker_seed = c->walker_seed;
       a.pt_metro = c->d_pt_metro();
-      a.pt_swap = c->d_pt_swap();
+      a.pt_q = c->d_pt_q();
       a.pt_slot = c->d_pt_slot();
       a.pt_acc = c->d_pt_acc();
       a.pt_M = c->pt_M;
-      a.pt_D = c->pt_D;
+      a.pt_spw = 64 / c->pt_M;
+      a.pt_minv = (uint32_t)(0xFFFFFFFFu / (uint32_t)c->pt_M + 1u);   // ceil(2^32 / M): lane / M = mulhi(lane, minv)
       hipError_t e = nfm::launch_pt_sweeps(c->group_L[g], a, (int)c->group_n_waves[g], c->stream);
       if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("pt_sweeps: ") + hipGetErrorString(e));
     }
@@ -1101,13 +1260,19 @@ nfm_status nfm_pt_set_slots(nfm_ctx* c, const int32_t* host_slots) {
   NFM_TRY(c, {
     const int M = c->pt_M;
     std::vector<char> seen(M);
-    for (int64_t s0 = 0; s0 < c->lay.total_walkers; s0 += M) {
-      std::fill(seen.begin(), seen.end(), 0);
-      for (int k = 0; k < M; ++k) {
-        const int32_t v = host_slots[s0 + k];
-        if (v < 0 || v >= M || seen[v]) return fail(c, NFM_EINVAL, "pt_set_slots: each set needs a permutation of 0..M-1");
-        seen[v] = 1;
+    const int spw = 64 / M;
+    for (int64_t w0 = 0; w0 < c->lay.total_walkers; w0 += 64) {
+      for (int g = 0; g < spw; ++g) {
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int k = 0; k < M; ++k) {
+          const int32_t v = host_slots[w0 + g * M + k];
+          if (v < 0 || v >= M || seen[v])
+            return fail(c, NFM_EINVAL, "pt_set_slots: each set needs a permutation of 0..M-1");
+          seen[v] = 1;
+        }
       }
+      for (int k = spw * M; k < 64; ++k)
+        if (host_slots[w0 + k] != 0) return fail(c, NFM_EINVAL, "pt_set_slots: idle walkers stay at slot 0");
     }
     NFM_HIP(c, hipMemcpyAsync(c->d_pt_slot(), host_slots, 4 * (size_t)c->lay.total_walkers, hipMemcpyHostToDevice,
                               c->stream));
@@ -1120,7 +1285,7 @@ nfm_status nfm_pt_read_exchanges(nfm_ctx* c, uint64_t* host_acc) {
   NFM_GUARD(c);
   if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_read_exchanges: call nfm_pt_init first");
   if (!host_acc) return fail(c, NFM_EINVAL, "pt_read_exchanges: null pointer");
-  const size_t n = (size_t)(c->lay.total_walkers / c->pt_M) * (size_t)(c->pt_M - 1);
+  const size_t n = (size_t)pt_sets_total(c) * (size_t)(c->pt_M - 1);
   NFM_HIP(c, hipMemcpyAsync(host_acc, c->d_pt_acc(), 8 * n, hipMemcpyDeviceToHost, c->stream));
   NFM_HIP(c, hipStreamSynchronize(c->stream));
   return NFM_OK;

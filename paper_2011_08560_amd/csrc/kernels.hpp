@@ -55,6 +55,14 @@ hipError_t launch_rec_seed_grid(RealInfo* reals, RecInfo* recs, int n_real, RecA
 hipError_t launch_rec_production(RealInfo* reals, RecInfo* recs, int n_real, RecArrays A, uint32_t* tables,
                                  int profile, double pl_dE, double pl_alpha, hipStream_t s);
 
+// wl.hip
+hipError_t launch_wl_init(RealInfo* reals, int n_real, WlArrays A, WlInfo* info, double ln_f0, uint32_t* tables,
+                          hipStream_t s);
+hipError_t launch_wl_update(RealInfo* reals, int n_real, WlArrays A, WlInfo* info, unsigned long long* hist,
+                            double flat_tol, double ln_f_final, uint32_t* tables, hipStream_t s);
+hipError_t launch_wl_to_rec(RealInfo* reals, RecInfo* recs, int n_real, RecArrays R, WlArrays A, const WlInfo* info,
+                            int profile, double pl_dE, double pl_alpha, hipStream_t s);
+
 // features.hip
 hipError_t launch_canonical_tables(RealInfo* reals, int n_real, double T, double* lnw, int32_t* k_lo, int32_t* k_top,
                                    uint32_t* tables, hipStream_t s);
@@ -73,6 +81,8 @@ hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uin
 // resident workgroups per CU of the persistent kernel (0 on error)
 int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode);
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s);
+// the exchange thresholds of realization r as the sweep kernel computes them (inspection)
+hipError_t launch_pt_swap_table(const double* q, int r, int M, int D, uint32_t* swap, hipStream_t s);
 bool sweep_supported(int L);
 
 }  // namespace nfm

@@ -73,11 +73,12 @@ struct SweepArgs {
   int32_t hist_n;
   uint64_t walker_seed;
   // parallel tempering (unused by the multicanonical kernel)
-  const uint32_t* pt_metro;  // M x 8 Metropolis thresholds, u-order
-  const uint32_t* pt_swap;   // (M - 1) x D exchange thresholds
+  const uint32_t* pt_metro;  // per realization kMaxReplicas x 8 Metropolis thresholds, u-order
+  const double* pt_q;        // per realization kMaxReplicas: q of the pair (s, s+1), exp(4 dbeta)
   int32_t* pt_slot;          // temperature slot of every walker
   uint64_t* pt_acc;          // accepted exchanges per (set, pair)
-  int32_t pt_M, pt_D;
+  int32_t pt_M, pt_spw;
+  uint32_t pt_minv, pt_pad;
 };
 
 // Weight-recursion state of one realization (device and host mirror, same layout as nfm_rec_info).
@@ -106,6 +107,23 @@ struct RecArrays {
   double* lnP;               // target profile used for the current weights
   double* lnW;               // current log-weights
   unsigned char* visited;    // level ever visited
+};
+
+// Wang-Landau state of one realization (device and host mirror, same layout as nfm_wl_info).
+struct WlInfo {
+  double ln_f;               // current modification factor
+  double flatness;           // min/mean of the stage histogram over its visited levels, last update
+  int32_t stage;             // halvings of ln f so far
+  int32_t done;              // ln f fell below the final value
+  int32_t k_top;             // the estimate lives on [0, k_top]; W is constant above
+  int32_t updates;           // updates so far
+};
+
+// Per-level arrays of the Wang-Landau estimate (indexed by level offset + level).
+struct WlArrays {
+  double* lng;               // ln g estimate
+  unsigned long long* hst;   // histogram of the current stage
+  double* lnw;               // log-weights -ln g of the current table
 };
 
 }  // namespace nfm

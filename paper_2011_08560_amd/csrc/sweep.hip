@@ -225,6 +225,21 @@ __device__ __forceinline__ void accept_level_spec(uint32_t rc, uint32_t th, int 
   F = Fn;
 }
 
+// Exchange threshold of slots (s, s+1) whose energies differ by 4d (Eq. (8)): q^d rounded down
+// to a multiple of 2^-32 (0xFFFFFFFF = always, d <= 0), q = exp(4 (beta_{s+1} - beta_s)) given by
+// the host, raised to d by binary powering (one FP64 product per bit and per squaring, lowest bit
+// first) -- products only, so the host reproduces every value bit for bit.
+__device__ __forceinline__ uint32_t pt_swap_threshold(double q, int d) {
+  if (d <= 0) return 0xFFFFFFFFu;
+  double r = 1.0, b = q;
+  while (d > 0) {
+    if (d & 1) r = r * b;
+    b = b * b;
+    d >>= 1;
+  }
+  return r >= 1.0 ? 0xFFFFFFFFu : (uint32_t)floor(ldexp(r, 32));
+}
+
 __device__ __forceinline__ int clamp_row(int B, int Bmax) {
   int R;
   asm("v_med3_i32 %0, %1, 0, %2" : "=v"(R) : "v"(B), "s"(Bmax));
@@ -232,9 +247,10 @@ __device__ __forceinline__ int clamp_row(int B, int Bmax) {
 }
 
 // PT = false: multicanonical sweeps; the table row follows the walker's level.
-// PT = true: parallel tempering (Sec. II, Eq. (8)); the walkers of a realization form sets of
-// M configurations, the row is the configuration's temperature slot, and after every sweep the
-// slots (s, s+1) with s = t (mod 2) try an exchange.
+// PT = true: parallel tempering (Sec. II, Eq. (8)); each wave of 64 walkers holds floor(64/M)
+// sets of M configurations (lanes g M .. g M + M - 1; the remaining lanes idle at slot 0, outside
+// exchanges and bookkeeping), the row is the configuration's temperature slot, and after every
+// sweep the slots (s, s+1) with s = t (mod 2) try an exchange. Temperatures are per realization.
 // XT (multicanonical, no speculation): the table is expanded on chip to one row per level of
 // the realization (rows outside the stored range repeat its edge rows, as the clamp would), so
 // the row of a level is the level itself and the decision needs no clamp.
@@ -271,13 +287,13 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   const uint32_t hbase = jbase + 4u * (uint32_t)jk_words(L);
   const int hlo = max(0, row0 - A.hist_margin), hn = A.hist_n;
   {
-    const uint32_t* gt = PT ? A.pt_metro : A.tables + RI.table_off;
+    const uint32_t* gt = A.tables + RI.table_off;
     for (int e = threadIdx.x; e < rows * 8; e += 64) {
       const int jj = e & 7;
       const int u = jj < 4 ? 3 - jj : (jj == 4 ? 7 : 11 - jj);
       int gr = e >> 3;   // row of the stored table
       if constexpr (XT) gr = min(max(gr - RI.row0, 0), RI.rows - 1);
-      const uint32_t v = gt[gr * 8 + u];
+      const uint32_t v = PT ? A.pt_metro[((int64_t)r * kMaxReplicas + gr) * 8 + u] : gt[gr * 8 + u];
       const uint32_t vp = (v == 0xFFFFFFFFu) ? v : (v ? v - 1u : 0u);
       *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = vp;
     }
@@ -306,6 +322,17 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       for (int w = 0; w < NWP; ++w)
 #pragma unroll
         for (int z = 0; z < L; ++z) lat(c, w)[z] = sp[(int64_t)((c * L + z) * NWP + w) * walkers];
+  }
+  // tempering: this lane's set within the wave (floor(lane / M)), its first lane, its index in
+  // the realization; lanes beyond the last whole set idle
+  uint32_t pt_base = 0, pt_set = 0;
+  bool pt_active = false;
+  if constexpr (PT) {
+    const uint32_t sw = __umulhi(threadIdx.x, A.pt_minv);
+    pt_active = sw < (uint32_t)A.pt_spw;
+    pt_base = sw * (uint32_t)A.pt_M;
+    pt_set = (uint32_t)(A.wave_wl[wave] >> 6) * (uint32_t)A.pt_spw + sw;
+    asm volatile("" : "+v"(pt_base), "+v"(pt_set));
   }
   const int E0 = A.ws.E[gw];
   int E = E0;        // tempering: the energy, updated per attempt
@@ -466,7 +493,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
         // Acceptance bits are shifted into F in site order, with a zero for every bit of a
         // field beyond the row's H sites, and applied to the plane-colour string once per word.
         uint32_t F = 0;
-        int Bq[4];
+        // levels after each attempt since the last window check (two groups of four)
+        int Bq[8];
         // speculative form: the pair for site 0 of the block is loaded at the block's start
         uint32_t p_rej = 0, p_acc = 0;
         int Racc_prev = R;
@@ -550,7 +578,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
               }
               hi_cur = hi_next;
             }
-            Bq[i] = B;
+            Bq[4 * (g & 1) + i] = B;
             // end of a row inside the word: zeros for the field's unused bits; end of the word
             // (or of the string): apply the flips
             const bool last_in_word = (q + 1 == Q) || (((((q + 1) / H) * FB + (q + 1) % H) >> 5) != w);
@@ -566,22 +594,26 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
           if (n_att == 2) philox_rounds<5, 10>(pr, kv);
           if (n_att == 3) philox_rounds<8, 10>(pr, kv);
           if constexpr (!PT) {
-            // Did an attempt of this group leave the window? Then replay the group exactly.
-            const int last = n_att - 1;
-            int bmin = Bq[0], bmax = Bq[0];
+            // Every second group (and at the block's end): did an attempt since the last check
+            // leave the window? Then replay those attempts' bookkeeping exactly.
+            if ((g & 1) == 1 || g + 1 == NG) {
+              const int g0 = g & ~1;                               // first group since the check
+              const int cnt = 4 * (g - g0) + n_att;                // attempts since the check
+              int bmin = Bq[0], bmax = Bq[0];
 #pragma unroll
-            for (int k = 1; k < 4; ++k) {
-              if (k > last) break;
-              bmin = min(bmin, Bq[k]);
-              bmax = max(bmax, Bq[k]);
-            }
-            if (bmin < win.lo || bmax > win.hi) {
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                if (k > last) break;
-                track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g + k), e_base, row0, e_bot, e_top);
+              for (int k = 1; k < 8; ++k) {
+                if (k >= cnt) break;
+                bmin = min(bmin, Bq[k]);
+                bmax = max(bmax, Bq[k]);
               }
-              win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+              if (bmin < win.lo || bmax > win.hi) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                  if (k >= cnt) break;
+                  track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g0 + k), e_base, row0, e_bot, e_top);
+                }
+                win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+              }
             }
           }
         }
@@ -595,23 +627,23 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     }
     if constexpr (PT) {
       // end of the Metropolis phase: bookkeeping with stamp (t + 1) N, trace
-      track_energy(te, E, (t + 1u) * (uint64_t)N, e_bot, e_top);
+      const int M = A.pt_M;
+      const bool active = pt_active;
+      if (active) track_energy(te, E, (t + 1u) * (uint64_t)N, e_bot, e_top);
       if (t - A.trace_t0 < (uint64_t)A.trace_cap) A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = E;
       // exchange phase: slots (s, s+1), s = t (mod 2), of each set of M lanes
-      const int M = A.pt_M;
-      const uint32_t base = threadIdx.x & ~(uint32_t)(M - 1);
+      const uint32_t base = pt_base;
       lds_store_i32(sE + 4u * (base + (uint32_t)slot), E);
       __syncthreads();
       const int par = (int)(t & 1u);
-      const bool lower = ((slot & 1) == par) && (slot + 1 < M);
-      const bool upper = (slot >= 1) && (((slot - 1) & 1) == par);
+      const bool lower = active && ((slot & 1) == par) && (slot + 1 < M);
+      const bool upper = active && (slot >= 1) && (((slot - 1) & 1) == par);
       int dec = 0;
       if (lower) {
         const int Eh = lds_load_i32(sE + 4u * (base + (uint32_t)slot + 1u));
         const int d = (Eh - E) / 4;   // energies of one realization share their residue mod 4
-        uint32_t th = 0xFFFFFFFFu;
-        if (d > 0) th = A.pt_swap[slot * A.pt_D + min(d, A.pt_D) - 1];
-        const uint32_t set = (uint32_t)wl / (uint32_t)M;
+        const uint32_t th = pt_swap_threshold(A.pt_q[(int64_t)r * kMaxReplicas + slot], d);
+        const uint32_t set = pt_set;   // set index within the realization
         const u32x4 rr = philox4x32_10_vk((uint32_t)(slot >> 2), (uint32_t)t, real_id, (set << 8) | kTagSwap, kv);
         const int k4 = slot & 3;
         const uint32_t rw = k4 == 0 ? rr.v[0] : k4 == 1 ? rr.v[1] : k4 == 2 ? rr.v[2] : rr.v[3];
@@ -665,8 +697,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     A.pt_slot[gw] = slot;
     // exchange counters of the pairs (s, s+1) of this lane's set, s = lane index in the set
     const int M = A.pt_M;
-    const int cidx = (int)(threadIdx.x & (uint32_t)(M - 1));
-    if (cidx < M - 1) A.pt_acc[(gw / M) * (M - 1) + cidx] += (uint64_t)lds_load_i32(sAcc + 4u * threadIdx.x);
+    const int cidx = (int)(threadIdx.x - pt_base);
+    if (pt_active && cidx < M - 1)   // global set index: walker offsets of realizations are multiples of 64
+      A.pt_acc[(int64_t)(RI.walker_off / 64 * A.pt_spw + pt_set) * (M - 1) + cidx] +=
+          (uint64_t)lds_load_i32(sAcc + 4u * threadIdx.x);
   } else {
     // the launch's histogram counts (at most 64 walkers x 2^20 sweeps per level)
     __syncthreads();
@@ -717,6 +751,20 @@ __global__ void __launch_bounds__(64) k_sweeps_queue(SweepArgs A, const int32_t*
       default: break;
     }
   }
+}
+
+// The exchange thresholds the sweep kernel uses for realization r, for inspection: [s][d - 1]
+// for d = 1..D.
+__global__ void k_pt_swap_table(const double* q, int r, int M, int D, uint32_t* swap) {
+  const double* qr = q + (int64_t)r * kMaxReplicas;
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < (M - 1) * D; f += gridDim.x * blockDim.x)
+    swap[f] = pt_swap_threshold(qr[f / D], f % D + 1);
+}
+
+hipError_t launch_pt_swap_table(const double* q, int r, int M, int D, uint32_t* swap, hipStream_t s) {
+  if (M < 2 || M > kMaxReplicas || D < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pt_swap_table, dim3(64), dim3(256), 0, s, q, r, M, D, swap);
+  return hipGetLastError();
 }
 
 __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
@@ -857,7 +905,9 @@ hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uin
 }
 
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s) {
-  if (a.pt_M < 2 || a.pt_M > kMaxReplicas || (a.pt_M & (a.pt_M - 1)) != 0 || a.pt_D < 1) return hipErrorInvalidValue;
+  if (a.pt_M < 2 || a.pt_M > kMaxReplicas || a.pt_spw != 64 / a.pt_M ||
+      a.pt_minv != 0xFFFFFFFFu / (uint32_t)a.pt_M + 1u)
+    return hipErrorInvalidValue;
   return launch_any(L, a, n_waves, 1, 0, 1, 0, false, true, s);
 }
 

@@ -40,6 +40,8 @@ REC_DTYPE = np.dtype([("k_lo", np.int32), ("k_top", np.int32), ("profile", np.in
                       ("iterations", np.int32), ("k_lo_changed", np.int32), ("pl_dE", np.float64),
                       ("pl_alpha", np.float64), ("flatness", np.float64), ("k_seed", np.int32),
                       ("pad", np.int32)], align=True)
+WL_DTYPE = np.dtype([("ln_f", np.float64), ("flatness", np.float64), ("stage", np.int32), ("done", np.int32),
+                     ("k_top", np.int32), ("updates", np.int32)], align=True)
 RT_SUMMARY_DTYPE = np.dtype([("tau_pop", np.float64), ("trips", np.uint64), ("n_used", np.int32),
                              ("n_censored", np.int32)], align=True)
 PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
@@ -110,14 +112,20 @@ def lib():
         "nfm_rec_init": (i32, [vp, i32, C.c_double, C.c_double]),
         "nfm_rec_update": (i32, [vp, C.c_double, vp]),
         "nfm_rec_production": (i32, [vp, i32, C.c_double, C.c_double]),
+        "nfm_wl_init": (i32, [vp, C.c_double]),
+        "nfm_wl_update": (i32, [vp, C.c_double, C.c_double, vp]),
+        "nfm_wl_get": (i32, [vp, i32, vp, vp, vp]),
+        "nfm_wl_to_rec": (i32, [vp, i32, C.c_double, C.c_double]),
         "nfm_rec_read_info": (i32, [vp, vp]),
         "nfm_rec_get_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "nfm_rec_set_state": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
         "nfm_set_tuning": (i32, [vp, vp]),
         "nfm_get_tuning": (i32, [vp, vp]),
         "nfm_pt_init": (i32, [vp, i32, vp]),
-        "nfm_pt_set_tables": (i32, [vp, vp, vp, i32]),
-        "nfm_pt_get_tables": (i32, [vp, vp, vp, C.POINTER(i32), C.POINTER(i32)]),
+        "nfm_pt_set_temps": (i32, [vp, i32, vp]),
+        "nfm_pt_get_temps": (i32, [vp, i32, vp]),
+        "nfm_pt_get_tables": (i32, [vp, i32, vp, vp, C.POINTER(i32), C.POINTER(i32)]),
+        "nfm_pt_adapt": (i32, [vp, C.c_double, C.c_double, vp, C.POINTER(i32)]),
         "nfm_pt_run_sweeps": (i32, [vp, u64]),
         "nfm_pt_read_slots": (i32, [vp, vp]),
         "nfm_pt_set_slots": (i32, [vp, vp]),
@@ -413,6 +421,27 @@ class Batch:
     def rec_production(self, profile: int, pl_dE: float = 96.0, pl_alpha: float = -3.6):
         self._check(self._lib.nfm_rec_production(self.ctx, profile, pl_dE, pl_alpha), "rec_production")
 
+    # Wang-Landau estimate
+    def wl_init(self, ln_f0: float = 1.0):
+        self._check(self._lib.nfm_wl_init(self.ctx, ln_f0), "wl_init")
+
+    def wl_update(self, flat_tol: float = 0.8, ln_f_final: float = 1e-4) -> np.ndarray:
+        info = np.zeros(self.n_real, WL_DTYPE)
+        self._check(self._lib.nfm_wl_update(self.ctx, flat_tol, ln_f_final, info.ctypes.data), "wl_update")
+        return info
+
+    def wl_get(self, r: int):
+        """(ln g, stage histogram, info) of realization r (3N/2 + 1 entries each)."""
+        n = 3 * int(self.Ls[r]) ** 3 // 2 + 1
+        lng = np.zeros(n, np.float64)
+        hst = np.zeros(n, np.uint64)
+        info = np.zeros(1, WL_DTYPE)
+        self._check(self._lib.nfm_wl_get(self.ctx, r, lng.ctypes.data, hst.ctypes.data, info.ctypes.data), "wl_get")
+        return lng, hst, info[0]
+
+    def wl_to_rec(self, profile: int = PROFILE_FLAT, pl_dE: float = 1.0, pl_alpha: float = 0.0):
+        self._check(self._lib.nfm_wl_to_rec(self.ctx, profile, pl_dE, pl_alpha), "wl_to_rec")
+
     def rec_read_info(self) -> np.ndarray:
         info = np.zeros(self.n_real, REC_DTYPE)
         self._check(self._lib.nfm_rec_read_info(self.ctx, info.ctypes.data), "rec_read_info")
@@ -475,21 +504,33 @@ class Batch:
         T = np.ascontiguousarray(temps, np.float64)
         self._check(self._lib.nfm_pt_init(self.ctx, len(T), T.ctypes.data), "pt_init")
 
-    def pt_tables(self):
-        """(metro [M, 8], swap [M-1, D]) as on the device."""
+    def pt_tables(self, r: int = 0):
+        """(metro [M, 8], swap [M-1, D]) of realization r, as the kernel computes them."""
         M, D = C.c_int32(), C.c_int32()
-        self._check(self._lib.nfm_pt_get_tables(self.ctx, None, None, C.byref(M), C.byref(D)), "pt_get_tables")
+        self._check(self._lib.nfm_pt_get_tables(self.ctx, r, None, None, C.byref(M), C.byref(D)), "pt_get_tables")
         metro = np.zeros((M.value, 8), np.uint32)
         swap = np.zeros((max(M.value - 1, 0), D.value), np.uint32)
-        self._check(self._lib.nfm_pt_get_tables(self.ctx, metro.ctypes.data, swap.ctypes.data, C.byref(M),
+        self._check(self._lib.nfm_pt_get_tables(self.ctx, r, metro.ctypes.data, swap.ctypes.data, C.byref(M),
                                                 C.byref(D)), "pt_get_tables")
         return metro, swap
 
-    def pt_set_tables(self, metro, swap):
-        metro = np.ascontiguousarray(metro, np.uint32)
-        swap = np.ascontiguousarray(swap, np.uint32)
-        self._check(self._lib.nfm_pt_set_tables(self.ctx, metro.ctypes.data, swap.ctypes.data, swap.shape[1]),
-                    "pt_set_tables")
+    def pt_set_temps(self, r: int, temps):
+        T = np.ascontiguousarray(temps, np.float64)
+        self._check(self._lib.nfm_pt_set_temps(self.ctx, r, T.ctypes.data), "pt_set_temps")
+
+    def pt_temps(self, r: int, M: int) -> np.ndarray:
+        T = np.zeros(M, np.float64)
+        self._check(self._lib.nfm_pt_get_temps(self.ctx, r, T.ctypes.data), "pt_get_temps")
+        return T
+
+    def pt_adapt(self, M: int, rate_lo: float = 0.4, rate_hi: float = 0.6):
+        """One adaptation step of every realization's temperatures toward a constant exchange
+        rate. Returns (rates [n_real, M-1] measured since the last step, pairs outside the band)."""
+        rates = np.zeros((self.n_real, M - 1), np.float64)
+        n_out = C.c_int32()
+        self._check(self._lib.nfm_pt_adapt(self.ctx, rate_lo, rate_hi, rates.ctypes.data, C.byref(n_out)),
+                    "pt_adapt")
+        return rates, n_out.value
 
     def pt_run_sweeps(self, n: int):
         self._check(self._lib.nfm_pt_run_sweeps(self.ctx, n), "pt_run_sweeps")
@@ -504,8 +545,8 @@ class Batch:
         self._check(self._lib.nfm_pt_set_slots(self.ctx, sl.ctypes.data), "pt_set_slots")
 
     def pt_exchanges(self, M: int) -> np.ndarray:
-        """Accepted exchanges, [n_walkers / M, M - 1]."""
-        out = np.zeros((self.n_walkers // M, M - 1), np.uint64)
+        """Accepted exchanges, [n_sets, M - 1], n_sets = (n_walkers / 64) floor(64 / M)."""
+        out = np.zeros(((self.n_walkers // 64) * (64 // M), M - 1), np.uint64)
         self._check(self._lib.nfm_pt_read_exchanges(self.ctx, out.ctypes.data), "pt_read_exchanges")
         return out
 
