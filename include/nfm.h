@@ -354,8 +354,9 @@ nfm_status nfm_sync(nfm_ctx* ctx);
  *   realization (over its sets and the sweeps that attempted the pair); host_rates (may be NULL)
  *   receives them, [n_real][M-1], and *n_outside (may be NULL) the number outside
  *   [rate_lo, rate_hi]. Then every gap beta_s - beta_{s+1} is multiplied by (-ln A_s)^(-1/4)
- *   (A_s clamped to [1e-6, 1 - 1e-12]; half the step that equalises A = exp(-c gap^2)) and
- *   the gaps are rescaled to their old sum, keeping T_0 and T_{M-1}; counters cleared.
+ *   (A_s clamped to [1e-6, 1 - 1e-12]; half the step that equalises A = exp(-c gap^2)), that
+ *   factor limited to [1/2, 2], and the gaps are rescaled to their old sum, keeping T_0 and
+ *   T_{M-1}; counters cleared.
  *   ESTATE before two PT sweeps since the last clear. */
 nfm_status nfm_pt_init(nfm_ctx* ctx, int32_t M, const double* host_temps);
 nfm_status nfm_pt_set_temps(nfm_ctx* ctx, int32_t r, const double* host_temps);

@@ -531,15 +531,16 @@ def pt_exchange_rates(acc_sets, t0, t1, M):
 def pt_adapt_step(T, rates):
     """One step of the temperature adaptation toward a constant exchange rate (a reading of the
     protocol the paper adopts, whose update it does not print): with gaps g_s = 1/T_s - 1/T_{s+1},
-    g_s <- g_s (-ln A_s)^(-1/4) (A_s clamped to [1e-6, 1 - 1e-12]), then all gaps rescaled to their
-    old sum so that T_0 and T_{M-1} stay."""
+    g_s <- g_s f_s, f_s = (-ln A_s)^(-1/4) limited to [1/2, 2] (A_s clamped to [1e-6, 1 - 1e-12]),
+    then all gaps rescaled to their old sum so that T_0 and T_{M-1} stay."""
     beta = [1.0 / float(x) for x in T]
     M = len(beta)
     span = beta[0] - beta[M - 1]
     gaps, total = [], 0.0
     for s in range(M - 1):
         a = min(max(float(rates[s]), 1e-6), 1.0 - 1e-12)
-        g = (beta[s] - beta[s + 1]) * (-math.log(a)) ** -0.25
+        f = min(max((-math.log(a)) ** -0.25, 0.5), 2.0)
+        g = (beta[s] - beta[s + 1]) * f
         gaps.append(g)
         total += g
     new = list(beta)

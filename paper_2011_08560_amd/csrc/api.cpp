@@ -1184,9 +1184,12 @@ nfm_status nfm_pt_adapt(nfm_ctx* c, double rate_lo, double rate_hi, double* host
         rate[s] = (double)a / ((double)ns * (double)((s % 2 == 0) ? n_even : n_odd));
         if (rate[s] < rate_lo || rate[s] > rate_hi) ++outside;
         if (host_rates) host_rates[(size_t)r * (M - 1) + s] = rate[s];
-        // A = exp(-c gap^2) would be equalised by gap / sqrt(-ln A); half that step in log space
+        // A = exp(-c gap^2) would be equalised by gap / sqrt(-ln A); half that step in log space,
+        // at most a factor of 2 either way (near A = 1 -- neighbours sharing the ground state --
+        // the Gaussian picture fails and the raw factor runs to 1000)
         const double a_c = std::min(std::max(rate[s], 1e-6), 1.0 - 1e-12);
-        gap[s] = (beta[s] - beta[s + 1]) * std::pow(-std::log(a_c), -0.25);
+        const double f = std::min(std::max(std::pow(-std::log(a_c), -0.25), 0.5), 2.0);
+        gap[s] = (beta[s] - beta[s + 1]) * f;
         total += gap[s];
       }
       const double bmax = beta[M - 1];

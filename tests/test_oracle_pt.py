@@ -192,6 +192,19 @@ def test_adapt_step_fixed_point_and_ends(orc):
     assert ratio[2] < ratio[0] < ratio[6]
 
 
+def test_adapt_step_factor_is_limited(orc):
+    # a pair that always exchanges (A = 1: both temperatures in the ground state) widens by 2 (not
+    # by (1e-12)^(-1/4) = 1000), one that never does narrows by (-ln 1e-6)^(-1/4), before the gaps
+    # are rescaled to their old sum
+    T = orc.pt_temperatures(4, 0.2, 3.2)
+    new = orc.pt_adapt_step(T, np.array([1.0, 0.0, np.exp(-1.0)]))
+    g_old, g_new = np.diff(1 / T), np.diff(1 / new)
+    k = g_new[2] / g_old[2]          # the pair with -ln A = 1 keeps its factor 1: k is the rescale
+    assert g_new[0] / g_old[0] == pytest.approx(2.0 * k, rel=1e-13)
+    assert g_new[1] / g_old[1] == pytest.approx(math.log(1e6) ** -0.25 * k, rel=1e-13)
+    assert np.sum(g_new) == pytest.approx(np.sum(g_old), rel=1e-14)
+
+
 def test_adapt_converges_to_equal_rates_on_a_gaussian_model(orc):
     # overlapping Gaussian energy distributions: A_s = exp(-c_s gap_s^2), c_s growing toward low T
     M = 12
