@@ -317,6 +317,21 @@ nfm_status nfm_autotune(nfm_ctx* ctx, int32_t calib_sweeps, const char* cache_pa
 
 nfm_status nfm_sync(nfm_ctx* ctx);
 
+/* Checkpoint and resume (the sweep counter travels with the state, so a run resumed from a
+ * checkpoint draws the same random words and gives the same spins, energies, histograms, round
+ * trips, traces, weights and tempering state as the run that was never interrupted).
+ * nfm_checkpoint_bytes: size of a checkpoint of this context (a header, the host-side scalars
+ *   and tempering temperatures, and a byte copy of the whole workspace).
+ * nfm_checkpoint: waits for all work queued on the stream, then writes the checkpoint into the
+ *   caller's host buffer of `capacity` bytes (NFM_ESIZE if smaller than nfm_checkpoint_bytes).
+ * nfm_restore: loads a checkpoint into a context created from the same batch description (sizes,
+ *   walkers, realization ids, seeds, trace capacity; NFM_EINVAL otherwise, NFM_ESIZE if
+ *   truncated), replacing its whole state, tuning included. The workspace may sit at another
+ *   device address or on another context of the same description. Synchronizes. */
+nfm_status nfm_checkpoint_bytes(const nfm_ctx* ctx, size_t* bytes);
+nfm_status nfm_checkpoint(nfm_ctx* ctx, void* host_blob, size_t capacity);
+nfm_status nfm_restore(nfm_ctx* ctx, const void* host_blob, size_t size);
+
 /* ---------------------------------------------------------------------------------------
  * Parallel tempering (Sec. II, Eq. (8)), the baseline the paper compares against. Each group
  * of 64 walkers of a realization (walkers 64q .. 64q + 63) holds floor(64/M) sets of M

@@ -18,7 +18,9 @@ simulation step runs in the library's kernels; this module only sequences calls.
 
 The second form is the scan of the power-law setting (Sec. II, Eq. (5)): the same realizations
 and converged estimates, one production run per (dE, alpha). The third compares the estimators of
-the density of states (the recursion of Sec. II and Wang-Landau) on sweeps to a flat histogram.
+the density of states (the recursion of Sec. II and Wang-Landau) on sweeps to a flat histogram;
+with --seed-train-L it also trains the seeding network on other realizations of those sizes and
+adds the recursion seeded by its guess.
 """
 from __future__ import annotations
 
@@ -31,7 +33,9 @@ import time
 import numpy as np
 
 from . import nfm
-from .seeding import iterate, make_batch
+from .seeding import canonical_features, generate, infer, iterate, make_batch, train
+
+CANON_BURN, CANON_SWEEPS = 100, 1000   # the seeding network's canonical run (T = 2)
 
 PT_TEMPS = [0.2 * 10.0 ** (m / 31.0) for m in range(32)]   # 32 temperatures geometric in [0.2, 2]
 PL_PAPER = (96.0, -3.6)                                      # the paper's setting of Eq. (5)
@@ -44,7 +48,7 @@ ADAPT_T = (0.2, 3.2)
 
 def converge(b, sweeps, f_tol, n_max, log=None):
     """Flat-target weight iteration until every realization converged once (or n_max rounds)."""
-    first = iterate(b, sweeps, f_tol, n_max, profile=(nfm.PROFILE_FLAT, 1.0, 0.0))
+    first = iterate(b, sweeps, f_tol, n_max, profile=(nfm.PROFILE_FLAT, 1.0, 0.0), log=log)
     if log:
         log(f"weight iteration: {int((first <= n_max).sum())}/{len(first)} converged, "
             f"median round {float(np.median(first)):.0f}")
@@ -55,12 +59,16 @@ def run_until_trips(b, run, min_trips, chunk, cap, log=None, what=""):
     """Run `run(chunk)` until every realization has min_trips round trips or `cap` sweeps have
     run. Returns (tau per realization in sweeps, NaN = censored; sweeps run)."""
     done = 0
+    t_log = time.time()
     while True:
         run(chunk)
         done += chunk
         tau, summ = b.rt_stats(min_trips=min_trips)
         if summ["n_censored"] == 0 or done >= cap:
             break
+        if log and time.time() - t_log > 60:
+            t_log = time.time()
+            log(f"{what}: {done} sweeps so far, {int(summ['n_censored'])} realizations short of {min_trips} trips")
     if log:
         log(f"{what}: {done} sweeps, {int(summ['n_used'])} realizations with >= {min_trips} trips, "
             f"{int(summ['n_censored'])} censored")
@@ -103,8 +111,15 @@ def tempering(b, L, min_trips, chunk, cap, burn=1000, adaptive=False, log=None):
         t0, t1 = ADAPT_T
         b.pt_init([t0 * (t1 / t0) ** (s / (M - 1)) for s in range(M)])
         rounds, rates = adapt_temperatures(b, M, log=log)
+        rates = np.asarray(rates).reshape(b.n_real, M - 1)
+        in_band = ((rates >= 0.4) & (rates <= 0.6)).all(axis=1)
+        q = np.quantile(rates, [0.05, 0.5, 0.95])
         extra = {"M": M, "adapt_rounds": rounds, "rates_min": float(rates.min()), "rates_max": float(rates.max()),
-                 "rates_mean": float(rates.mean())}
+                 "rates_mean": float(rates.mean()), "rates_q05_q50_q95": [float(x) for x in q],
+                 "realizations_in_band": int(in_band.sum())}
+        if log:
+            log(f"pt adaptation: {int(in_band.sum())}/{b.n_real} realizations with every rate in [0.4, 0.6]; "
+                f"rate quantiles 5/50/95 % {q[0]:.3f}/{q[1]:.3f}/{q[2]:.3f}")
     else:
         M = len(PT_TEMPS)
         b.pt_init(PT_TEMPS)
@@ -195,12 +210,13 @@ def scan(L, n_real, dEs, alphas, min_trips=100, iter_sweeps=None, f_tol=0.5, n_m
 
 
 def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0.8, wl_ln_f0=None, wl_final=None,
-               wl_max_steps=2000, first_id=0, log=None):
+               wl_max_steps=2000, first_id=0, mlp=None, log=None):
     """Sweeps each estimator needs until its flat-target weights give a flat histogram (f_tol) on
     the same realizations: the recursion from W = 1, and Wang-Landau (steps of wl_sweeps, ln f
     from wl_ln_f0 halved at flatness wl_flat down to wl_final) handed to the recursion, which then
-    runs its rounds until the same convergence test passes. Rounds run 10 % extra thermalization
-    sweeps, counted. Returns a JSON-able record with per-realization totals.
+    runs its rounds until the same convergence test passes; with a trained seeding network `mlp`
+    also the recursion seeded by its guess (its canonical run's sweeps counted). Rounds run 10 %
+    extra thermalization sweeps, counted. Returns a JSON-able record with per-realization totals.
 
     The batched update adds ln f per counted visit but only after a whole step, so ln f0 is sized
     to raise a level by about one per step at an even spread over the 3N/2 + 1 levels (a first
@@ -235,6 +251,25 @@ def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0
     if log:
         log(f"wang-landau: {int((done_at > 0).sum())}/{n_real} reached ln f < {wl_final}, "
             f"{int(wl_ok.sum())} converged after the hand-over, median {np.nanmedian(wl_total):.0f} sweeps")
+    seeded, k_seed, fallback = None, None, None
+    if mlp is not None:
+        b = make_batch([L] * n_real, first_real_id=first_id)
+        x = canonical_features(b, burn=CANON_BURN, sweeps=CANON_SWEEPS)
+        mlp.to_bf16()
+        curves = infer(mlp, x)
+        b.rec_init(nfm.PROFILE_FLAT, 1.0, 0.0)
+        k_seed = np.asarray(b.rec_seed_grid(curves))
+        it = iterate(b, sweeps, f_tol, n_max, initialized=True, log=log)
+        b.close()
+        # a seeded start that has not converged by n_max rounds falls back to the plain start: its
+        # cost is then the n_max rounds spent plus the plain arm's sweeps
+        canon = CANON_BURN + CANON_SWEEPS
+        fallback = it > n_max
+        seeded = np.where(fallback, canon + n_max * per_round + plain, canon + it * per_round).astype(float)
+        if log:
+            log(f"seeded recursion: {int((~fallback).sum())}/{n_real} converged from the seed, "
+                f"{int(fallback.sum())} fell back to the plain start, median {np.nanmedian(seeded):.0f} sweeps, "
+                f"{int((k_seed < 0).sum())} seeds rejected")
     both = np.isfinite(plain) & np.isfinite(wl_total)
 
     def arm(x):
@@ -247,7 +282,27 @@ def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0
                    "rounds_after_handover_median": float(np.median(after[after <= n_max])) if (after <= n_max).any() else None},
             "recursion_sweeps": arm(plain), "wang_landau_sweeps": arm(wl_total),
             "paired": int(both.sum()), "wl_fewer": int((wl_total[both] < plain[both]).sum()),
-            "wl_more": int((wl_total[both] > plain[both]).sum())}
+            "wl_more": int((wl_total[both] > plain[both]).sum()),
+            **({} if seeded is None else {
+                "mlp_seeded_sweeps": arm(seeded), "seed_rejected": int((k_seed < 0).sum()),
+                "seed_fallback": int(fallback.sum()),
+                "seeded_fewer": int((seeded[np.isfinite(seeded) & np.isfinite(plain)]
+                                     < plain[np.isfinite(seeded) & np.isfinite(plain)]).sum()),
+                "seeded_more": int((seeded[np.isfinite(seeded) & np.isfinite(plain)]
+                                    > plain[np.isfinite(seeded) & np.isfinite(plain)]).sum())})}
+
+
+def train_seed_network(Ls, n_real, sweeps, f_tol, n_max, epochs=40, seed=7, first_id=0, log=None):
+    """A seeding network trained on converged estimates of n_real realizations of the sizes Ls
+    (ids from first_id on)."""
+    per_L = int(math.ceil(n_real / len(Ls)))
+    x, y, m, stats = generate(Ls, per_L, sweeps, f_tol, n_max, first_id=first_id, log=log)
+    mlp = nfm.Mlp(batch_max=256)
+    mlp.init(seed)
+    losses, val = train(mlp, x, y, m, epochs=epochs, seed=seed)
+    if log:
+        log(f"seeding network: {len(Ls)} sizes, loss {losses[-1]:.4g}, validation {val}")
+    return mlp, {"L": list(Ls), "per_L": stats, "final_loss": losses[-1], "val_loss": val}
 
 
 def main(argv=None):
@@ -268,13 +323,23 @@ def main(argv=None):
     ap.add_argument("--scan-alpha", type=float, nargs="*")
     ap.add_argument("--estimators", action="store_true",
                     help="compare the recursion with Wang-Landau on sweeps to a flat histogram")
+    ap.add_argument("--seed-train-L", type=int, nargs="*",
+                    help="with --estimators: also the recursion seeded by a network trained on these sizes")
+    ap.add_argument("--seed-train-real", type=int, default=2048)
     args = ap.parse_args(argv)
     t0 = time.time()
     log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
     for L in args.L:
         if args.estimators:
-            rec = estimators(L, args.real, args.iter_sweeps or 1000 * L * L, args.f_tol, args.n_max,
-                             first_id=args.first_id, log=log)
+            sw = args.iter_sweeps or 1000 * L * L
+            mlp, net = None, None
+            if args.seed_train_L:
+                # training realizations from ids beyond the compared ones
+                mlp, net = train_seed_network(args.seed_train_L, args.seed_train_real, sw, args.f_tol, args.n_max,
+                                              first_id=args.first_id + args.real, log=log)
+            rec = estimators(L, args.real, sw, args.f_tol, args.n_max, first_id=args.first_id, mlp=mlp, log=log)
+            if net:
+                rec["seed_network"] = net
         elif args.scan_dE and args.scan_alpha:
             rec = scan(L, args.real, args.scan_dE, args.scan_alpha, args.min_trips, args.iter_sweeps or None,
                        args.f_tol, args.n_max, args.chunk or None, args.cap or None, args.first_id, log)

@@ -710,6 +710,122 @@ nfm_status nfm_sync(nfm_ctx* c) {
   return NFM_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Checkpoint / resume. Blob: header, the host scalars of the context, its tempering
+// temperatures, then a byte copy of the whole device workspace (every device structure in it
+// holds offsets, not addresses, so the copy is valid at any workspace address).
+namespace {
+constexpr char kCkptMagic[8] = {'N', 'F', 'M', 'C', 'K', 'P', 'T', '1'};
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, n_real;
+  uint64_t disorder_seed, walker_seed, batch_hash, workspace_bytes;
+  int32_t trace_cap, couplings, speculate, hist_mode;
+  uint32_t sweeps_per_launch;
+  int32_t schedule, waves_per_cu, rec_ready, pt_M, wl_ready;
+  uint64_t sweeps, trace_t0, pt_t_reset;
+};
+
+// FNV-1a over every realization's size, walker count and id: the layout of the workspace
+uint64_t batch_hash(const nfm_ctx* c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xFF);
+      h *= 1099511628211ull;
+    }
+  };
+  for (const auto& r : c->reals) {
+    mix(r.L);
+    mix(r.walkers);
+    mix(r.real_id);
+  }
+  return h;
+}
+
+size_t ckpt_bytes(const nfm_ctx* c) {
+  return sizeof(CkptHeader) + sizeof(double) * (size_t)c->n_real * nfm::kMaxReplicas + c->lay.total;
+}
+}  // namespace
+
+nfm_status nfm_checkpoint_bytes(const nfm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return NFM_EINVAL;
+  *bytes = ckpt_bytes(c);
+  return NFM_OK;
+}
+
+nfm_status nfm_checkpoint(nfm_ctx* c, void* host_blob, size_t capacity) {
+  NFM_GUARD(c);
+  if (!host_blob) return fail(c, NFM_EINVAL, "checkpoint: null buffer");
+  if (capacity < ckpt_bytes(c)) return fail(c, NFM_ESIZE, "checkpoint: buffer smaller than nfm_checkpoint_bytes()");
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.n_real = (uint32_t)c->n_real;
+  h.disorder_seed = c->disorder_seed;
+  h.walker_seed = c->walker_seed;
+  h.batch_hash = batch_hash(c);
+  h.workspace_bytes = c->lay.total;
+  h.trace_cap = c->trace_cap;
+  h.couplings = c->couplings ? 1 : 0;
+  h.speculate = c->speculate;
+  h.hist_mode = c->hist_mode;
+  h.sweeps_per_launch = c->sweeps_per_launch;
+  h.schedule = c->schedule;
+  h.waves_per_cu = c->waves_per_cu;
+  h.rec_ready = c->rec_ready ? 1 : 0;
+  h.pt_M = c->pt_M;
+  h.wl_ready = c->wl_ready ? 1 : 0;
+  h.sweeps = c->sweeps;
+  h.trace_t0 = c->trace_t0;
+  h.pt_t_reset = c->pt_t_reset;
+  char* out = (char*)host_blob;
+  std::memcpy(out, &h, sizeof(h));
+  double* T = (double*)(out + sizeof(h));
+  const size_t nT = (size_t)c->n_real * nfm::kMaxReplicas;
+  for (size_t i = 0; i < nT; ++i) T[i] = i < c->pt_T.size() ? c->pt_T[i] : 0.0;
+  // everything queued on the stream so far is part of the state
+  NFM_HIP(c, hipMemcpyAsync(out + sizeof(h) + sizeof(double) * nT, c->ws, c->lay.total, hipMemcpyDeviceToHost,
+                            c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
+  NFM_GUARD(c);
+  if (!host_blob || size < sizeof(CkptHeader)) return fail(c, NFM_EINVAL, "restore: no checkpoint");
+  CkptHeader h;
+  std::memcpy(&h, host_blob, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    return fail(c, NFM_EINVAL, "restore: not a checkpoint of this library version");
+  if (h.n_real != (uint32_t)c->n_real || h.batch_hash != batch_hash(c) || h.workspace_bytes != c->lay.total ||
+      h.disorder_seed != c->disorder_seed || h.walker_seed != c->walker_seed || h.trace_cap != c->trace_cap)
+    return fail(c, NFM_EINVAL, "restore: checkpoint of a different batch (sizes, walkers, ids, seeds or trace)");
+  if (size < ckpt_bytes(c)) return fail(c, NFM_ESIZE, "restore: checkpoint truncated");
+  NFM_TRY(c, {
+    const char* in = (const char*)host_blob;
+    const size_t nT = (size_t)c->n_real * nfm::kMaxReplicas;
+    NFM_HIP(c, hipMemcpyAsync(c->ws, in + sizeof(h) + sizeof(double) * nT, c->lay.total, hipMemcpyHostToDevice,
+                              c->stream));
+    NFM_HIP(c, hipStreamSynchronize(c->stream));
+    const double* T = (const double*)(in + sizeof(h));
+    c->pt_T.assign(T, T + nT);
+    c->couplings = h.couplings != 0;
+    c->speculate = h.speculate;
+    c->hist_mode = h.hist_mode;
+    c->sweeps_per_launch = h.sweeps_per_launch;
+    c->schedule = h.schedule;
+    c->waves_per_cu = h.waves_per_cu;
+    c->rec_ready = h.rec_ready != 0;
+    c->pt_M = h.pt_M;
+    c->wl_ready = h.wl_ready != 0;
+    c->sweeps = h.sweeps;
+    c->trace_t0 = h.trace_t0;
+    c->pt_t_reset = h.pt_t_reset;
+    return pull_reals(c);   // table rows, bounds and energies base as the checkpoint had them
+  })
+}
+
 
 nfm_status nfm_set_histograms(nfm_ctx* c, const uint64_t* host_src) {
   NFM_GUARD(c);

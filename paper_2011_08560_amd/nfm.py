@@ -107,6 +107,9 @@ def lib():
         "nfm_read_trace": (i32, [vp, vp, C.POINTER(i32)]),
         "nfm_reset_trace": (i32, [vp]),
         "nfm_sync": (i32, [vp]),
+        "nfm_checkpoint_bytes": (i32, [vp, C.POINTER(sz)]),
+        "nfm_checkpoint": (i32, [vp, vp, sz]),
+        "nfm_restore": (i32, [vp, vp, sz]),
         "nfm_set_histograms": (i32, [vp, vp]),
         "nfm_reset_round_trips": (i32, [vp]),
         "nfm_rec_init": (i32, [vp, i32, C.c_double, C.c_double]),
@@ -400,6 +403,19 @@ class Batch:
 
     def sync(self):
         self._check(self._lib.nfm_sync(self.ctx), "sync")
+
+    def checkpoint(self) -> np.ndarray:
+        """The whole state of the context as a host byte array (nfm_checkpoint)."""
+        n = C.c_size_t()
+        self._check(self._lib.nfm_checkpoint_bytes(self.ctx, C.byref(n)), "checkpoint_bytes")
+        blob = np.empty(n.value, np.uint8)
+        self._check(self._lib.nfm_checkpoint(self.ctx, blob.ctypes.data, n.value), "checkpoint")
+        return blob
+
+    def restore(self, blob: np.ndarray):
+        """Load a checkpoint of a batch with the same description (nfm_restore)."""
+        blob = np.ascontiguousarray(blob, np.uint8)
+        self._check(self._lib.nfm_restore(self.ctx, blob.ctypes.data, blob.size), "restore")
 
     # weight recursion
     def set_histograms(self, H: np.ndarray):

@@ -55,15 +55,17 @@ def canonical_features(b, T=2.0, burn=100, sweeps=1000):
     return x
 
 
-def iterate(b, n_sweeps, f_tol=0.5, n_max=50, profile=(0, 1.0, 0.0), initialized=False, therm=0.1):
+def iterate(b, n_sweeps, f_tol=0.5, n_max=50, profile=(0, 1.0, 0.0), initialized=False, therm=0.1, log=None):
     """Weight iterations until every realization has converged once or n_max rounds: each round
     runs therm * n_sweeps sweeps under the new weights before its n_sweeps measured sweeps (the
     update reads the histogram as equilibrium data). Returns the round (1-based) at which each
-    realization first converged; n_max + 1 = censored."""
+    realization first converged; n_max + 1 = censored. log (optional) receives a line per round
+    once a minute."""
     if not initialized:
         b.rec_init(*profile)
     first = np.full(b.n_real, n_max + 1, np.int64)
     n_therm = int(round(therm * n_sweeps))
+    t_log = time.time()
     for it in range(1, n_max + 1):
         if n_therm:
             b.run_sweeps(n_therm)
@@ -72,6 +74,9 @@ def iterate(b, n_sweeps, f_tol=0.5, n_max=50, profile=(0, 1.0, 0.0), initialized
         info = b.rec_update(f_tol)
         newly = (info["converged"] == 1) & (first > n_max)
         first[newly] = it
+        if log and time.time() - t_log > 60:
+            t_log = time.time()
+            log(f"weight iteration round {it}: {int((first <= n_max).sum())}/{b.n_real} converged")
         if (first <= n_max).all():
             break
     return first

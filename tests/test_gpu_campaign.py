@@ -98,3 +98,17 @@ def test_estimators_run(campaign):
     assert rec["recursion_sweeps"]["converged"] == 32, rec
     assert rec["wang_landau_sweeps"]["converged"] == 32, rec
     assert rec["paired"] == 32 and rec["wl_fewer"] + rec["wl_more"] <= 32
+
+
+def test_estimators_with_seed_network(campaign):
+    log = lambda s: print(s, flush=True)
+    mlp, net = campaign.train_seed_network([4], 256, 2000, 0.5, 40, epochs=20, first_id=2000, log=log)
+    rec = campaign.estimators(4, 32, 2000, n_max=40, wl_sweeps=200, first_id=500, mlp=mlp, log=log)
+    print(rec, flush=True)
+    # with the fallback to the plain start every realization converges; few need it, and the
+    # seed saves sweeps for most
+    assert rec["mlp_seeded_sweeps"]["converged"] == 32, rec
+    assert rec["seed_fallback"] <= 3, rec
+    assert rec["seeded_fewer"] > rec["seeded_more"], rec
+    # the seeded arm pays for its canonical run
+    assert rec["mlp_seeded_sweeps"]["median"] >= campaign.CANON_BURN + campaign.CANON_SWEEPS
