@@ -326,9 +326,27 @@ def main(argv=None):
     ap.add_argument("--seed-train-L", type=int, nargs="*",
                     help="with --estimators: also the recursion seeded by a network trained on these sizes")
     ap.add_argument("--seed-train-real", type=int, default=2048)
+    ap.add_argument("--save-tau", help="comparison: write every method's per-realization times to this .npz")
+    ap.add_argument("--analyse", nargs="+", metavar="NPZ",
+                    help="no simulation: pool the methods of earlier --save-tau files (same L, realizations "
+                         "and seeds; a later file's method replaces an earlier one's) and analyse them")
     args = ap.parse_args(argv)
     t0 = time.time()
     log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
+    if args.analyse:
+        taus, cap = {}, {}
+        for path in args.analyse:
+            with np.load(path, allow_pickle=False) as z:
+                for k in z.files:
+                    if k.startswith("tau_"):
+                        taus[k[4:]] = z[k]
+                    elif k.startswith("sweeps_"):
+                        cap[k[7:]] = int(z[k])
+        rec = {"sources": args.analyse, "sweeps_run": cap,
+               "censored": {m: int((~np.isfinite(t)).sum()) for m, t in taus.items()},
+               "analysis": analyse(taus, eps=args.eps, blocks=args.blocks)}
+        print(json.dumps(rec), flush=True)
+        return
     for L in args.L:
         if args.estimators:
             sw = args.iter_sweeps or 1000 * L * L
@@ -346,7 +364,11 @@ def main(argv=None):
         else:
             rec = compare(L, args.real, args.methods, args.min_trips, args.iter_sweeps or None, args.f_tol,
                           args.n_max, args.chunk or None, args.cap or None, args.first_id, args.eps, args.blocks, log)
-            rec.pop("tau")
+            tau = rec.pop("tau")
+            if args.save_tau:
+                np.savez(args.save_tau, **{f"tau_{m}": np.array([np.nan if x is None else x for x in t], float)
+                                          for m, t in tau.items()},
+                         **{f"sweeps_{m}": np.int64(v) for m, v in rec["sweeps_run"].items()})
         rec["wall_s"] = time.time() - t0
         print(json.dumps(rec), flush=True)
 
