@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--walkers", type=int, default=0, help="walkers per realization (default: the config's)")
     ap.add_argument("--speculate", type=int, default=-1, choices=[-1, 0, 1],
                     help="speculative table lookups: -1 automatic, 0 off, 1 on")
+    ap.add_argument("--ws", type=int, default=0, choices=[0, 1, 2],
+                    help="generator wave beside each sampling wave: 0 automatic, 1 never, 2 always")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a reference dispatch of known traffic "
@@ -168,7 +170,7 @@ def main():
         tuned, _ = b.autotune(calib_sweeps=256)
     else:
         # 1000 sweeps per launch: the rounds of 1e4 / 1e5 sweeps split into equal launches
-        b.set_tuning(speculate=args.speculate, sweeps_per_launch=min(1000, S))
+        b.set_tuning(speculate=args.speculate, sweeps_per_launch=min(1000, S), ws=args.ws)
     stream = torch.cuda.current_stream()
     attempts_per_step = W * S * sum(l ** 3 for l in Ls)
     tn = b.get_tuning()
@@ -207,8 +209,7 @@ def main():
     attempts_per_launch = attempts_per_step / launches_per_step
     achieved = ALG_OPS_PER_ATTEMPT * attempts_per_launch / avg_launch_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
-    kernel = ("k_sweeps<%d,PT>" % L) if pt else ("k_sweeps_queue" if tuned and tuned["schedule"] == 1
-                                                  else "k_sweeps<%d>" % L)
+    kernel = b.last_kernel()   # the form the library chose for the timed launches
 
     line = {
         "metric": "spin-flip attempts/s per GPU",
@@ -235,7 +236,7 @@ def main():
                      "traffic": measured_traffic(args.config, tn["sweeps_per_launch"]) if S % tn["sweeps_per_launch"] == 0
                      else None,
                      "kernel": kernel, "avg_launch_ms": avg_launch_s * 1e3,
-                     "alg_ops_per_attempt": ALG_OPS_PER_ATTEMPT, "speculate": args.speculate},
+                     "alg_ops_per_attempt": ALG_OPS_PER_ATTEMPT, "speculate": args.speculate, "ws": args.ws},
     }
     if info is not None:
         line["weight_iterations"] = {"done": int(info["iterations"].max()),

@@ -288,20 +288,26 @@ nfm_status nfm_wl_to_rec(nfm_ctx* ctx, int32_t profile, double pl_dE, double pl_
  *     when that leaves as many workgroups resident per compute unit as the window (capped at the
  *     ones the launch needs), else the window; 1 window: the table's rows and 64 levels on either
  *     side, levels outside it counted in device memory directly; 2 every level; 3 the table's
- *     rows alone (the most direct counting; for tests of that path). */
+ *     rows alone (the most direct counting; for tests of that path).
+ *   ws: per-size launches with the expanded table only: a second wave per workgroup computes the
+ *     sampling wave's random words into LDS, two plane blocks ahead (the same words, so the same
+ *     results). 0 automatic: when the launch has at most one wave of walkers per SIMD and all its
+ *     workgroups fit at once; 1 never; 2 always. */
 typedef struct {
   int32_t speculate;
   int32_t sweeps_per_launch;
   int32_t schedule;
   int32_t waves_per_cu;
   int32_t hist;
+  int32_t ws;
 } nfm_tuning;
 nfm_status nfm_set_tuning(nfm_ctx* ctx, const nfm_tuning* tuning);
 nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
 
 /* Autotuner for mixed batches (no passage of the paper: a launch-configuration search). Times
  * every candidate tuning (speculation off/on x sweeps per launch {64, 256, 1024} x {per-size
- * launches, persistent queue with as many workgroups as fit, 4 or 8 per CU}) for calib_sweeps
+ * launches without and (no speculation) with the generator wave, persistent queue with as many
+ * workgroups as fit, 4 or 8 per CU}) for calib_sweeps
  * sweeps on the batch itself, then restores spins, walker state and histograms, so the
  * calibration leaves no trace in the results (the sweep counter does not move). The fastest
  * candidate (spin-flip attempts per second) is applied and returned in *best. Results are cached
@@ -316,6 +322,9 @@ nfm_status nfm_autotune(nfm_ctx* ctx, int32_t calib_sweeps, const char* cache_pa
                         int32_t max_results, int32_t* n_results, nfm_tuning* best);
 
 nfm_status nfm_sync(nfm_ctx* ctx);
+/* Name of the sweep kernel form the last sweep launch on the calling host thread used, e.g.
+ * "k_sweeps_ws<6>" (a report for benchmarks; "none" before any launch). */
+const char* nfm_last_kernel(const nfm_ctx* ctx);
 
 /* Checkpoint and resume (the sweep counter travels with the state, so a run resumed from a
  * checkpoint draws the same random words and gives the same spins, energies, histograms, round

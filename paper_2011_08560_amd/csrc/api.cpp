@@ -132,6 +132,7 @@ struct nfm_ctx {
   bool couplings = false;
   int speculate = -1;                      // -1 auto, 0 off, 1 on
   int hist_mode = 0;                       // on-chip histogram: 0 auto, 1 window, 2 every level, 3 rows
+  int ws_mode = 0;                         // generator wave: 0 auto, 1 never, 2 always
   uint32_t sweeps_per_launch = kMaxSweepsPerLaunch;
   int schedule = 0;                        // 0: one launch per lattice size, 1: persistent work queue
   int waves_per_cu = 0;                    // persistent grid: workgroups per CU (0 = as many as fit)
@@ -577,7 +578,7 @@ static nfm::SweepArgs muca_args(nfm_ctx* c, uint64_t t0, uint32_t n, int trace_c
 
 // Launch n multicanonical sweeps starting at sweep t0 under the given tuning (no checks).
 static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int speculate, uint32_t per_launch,
-                                int schedule, int waves_per_cu, int hist_mode, int trace_cap) {
+                                int schedule, int waves_per_cu, int hist_mode, int ws_mode, int trace_cap) {
   int lds_all = 1, k_all = 1;
   for (const auto& ri : c->reals) {
     lds_all = std::max(lds_all, ri.rows);
@@ -611,7 +612,7 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
         // overlapped with generator work, which costs fewer instructions than a second read.
         const bool spec = speculate == 1;
         hipError_t e = nfm::launch_muca_sweeps(L, a, (int)c->group_n_waves[g], lds_rows, hist_levels, c->n_cu,
-                                                     hist_mode, spec, c->stream);
+                                                     hist_mode, ws_mode, spec, c->stream);
         if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_sweeps: ") + hipGetErrorString(e));
       }
     }
@@ -628,7 +629,7 @@ nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
   if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
     return fail(c, NFM_ERANGE, "run_sweeps: the sweep counter must stay below 2^32");
   nfm_status st = muca_launches(c, c->sweeps, n_sweeps, c->speculate, c->sweeps_per_launch, c->schedule,
-                                c->waves_per_cu, c->hist_mode, c->trace_cap);
+                                c->waves_per_cu, c->hist_mode, c->ws_mode, c->trace_cap);
   if (st != NFM_OK) return st;
   c->sweeps += n_sweeps;
   return NFM_OK;
@@ -704,6 +705,8 @@ nfm_status nfm_reset_trace(nfm_ctx* c) {
   return NFM_OK;
 }
 
+const char* nfm_last_kernel(const nfm_ctx* c) { return c ? nfm::last_sweep_kernel() : "none"; }
+
 nfm_status nfm_sync(nfm_ctx* c) {
   NFM_GUARD(c);
   NFM_HIP(c, hipStreamSynchronize(c->stream));
@@ -720,7 +723,7 @@ struct CkptHeader {
   char magic[8];
   uint32_t version, n_real;
   uint64_t disorder_seed, walker_seed, batch_hash, workspace_bytes;
-  int32_t trace_cap, couplings, speculate, hist_mode;
+  int32_t trace_cap, couplings, speculate, hist_mode, ws_mode, pad;
   uint32_t sweeps_per_launch;
   int32_t schedule, waves_per_cu, rec_ready, pt_M, wl_ready;
   uint64_t sweeps, trace_t0, pt_t_reset;
@@ -770,6 +773,7 @@ nfm_status nfm_checkpoint(nfm_ctx* c, void* host_blob, size_t capacity) {
   h.couplings = c->couplings ? 1 : 0;
   h.speculate = c->speculate;
   h.hist_mode = c->hist_mode;
+  h.ws_mode = c->ws_mode;
   h.sweeps_per_launch = c->sweeps_per_launch;
   h.schedule = c->schedule;
   h.waves_per_cu = c->waves_per_cu;
@@ -813,6 +817,7 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
     c->couplings = h.couplings != 0;
     c->speculate = h.speculate;
     c->hist_mode = h.hist_mode;
+    c->ws_mode = h.ws_mode;
     c->sweeps_per_launch = h.sweeps_per_launch;
     c->schedule = h.schedule;
     c->waves_per_cu = h.waves_per_cu;
@@ -1002,15 +1007,16 @@ nfm_status nfm_set_tuning(nfm_ctx* c, const nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
   if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0 || t->sweeps_per_launch > (1 << 20) ||
       t->schedule < 0 || t->schedule > 1 ||
-      t->waves_per_cu < 0 || t->waves_per_cu > 64 || t->hist < 0 || t->hist > 3)
+      t->waves_per_cu < 0 || t->waves_per_cu > 64 || t->hist < 0 || t->hist > 3 || t->ws < 0 || t->ws > 2)
     return fail(c, NFM_EINVAL,
                 "set_tuning: speculate in {-1,0,1}, sweeps_per_launch in [0, 2^20], schedule in {0,1}, waves_per_cu in "
-                "[0,64], hist in {0,1,2,3}");
+                "[0,64], hist in {0,1,2,3}, ws in {0,1,2}");
   c->speculate = t->speculate;
   c->sweeps_per_launch = t->sweeps_per_launch == 0 ? kMaxSweepsPerLaunch : (uint32_t)t->sweeps_per_launch;
   c->schedule = t->schedule;
   c->waves_per_cu = t->waves_per_cu;
   c->hist_mode = t->hist;
+  c->ws_mode = t->ws;
   return NFM_OK;
 }
 
@@ -1021,6 +1027,7 @@ nfm_status nfm_get_tuning(const nfm_ctx* c, nfm_tuning* t) {
   t->schedule = c->schedule;
   t->waves_per_cu = c->waves_per_cu;
   t->hist = c->hist_mode;
+  t->ws = c->ws_mode;
   return NFM_OK;
 }
 
@@ -1068,7 +1075,8 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
         std::istringstream is(line);
         std::string k;
         nfm_tuning t{};
-        if ((is >> k >> t.speculate >> t.sweeps_per_launch >> t.schedule >> t.waves_per_cu >> t.hist) && k == key) {
+        if ((is >> k >> t.speculate >> t.sweeps_per_launch >> t.schedule >> t.waves_per_cu >> t.hist >> t.ws) &&
+            k == key) {
           hit = t;
           found = 1;
         }
@@ -1091,10 +1099,12 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     const int chunks[] = {64, 256, 1024};
     for (int spec = 0; spec <= 1; ++spec)
       for (int ch : chunks) {
-        cand.push_back(nfm_tuning{spec, ch, 0, 0, 0});
-        cand.push_back(nfm_tuning{spec, ch, 1, 0, 0});
+        // per-size launches: with and without the generator wave (speculation has none)
+        cand.push_back(nfm_tuning{spec, ch, 0, 0, 0, 1});
+        if (!spec) cand.push_back(nfm_tuning{spec, ch, 0, 0, 0, 2});
+        cand.push_back(nfm_tuning{spec, ch, 1, 0, 0, 0});
         for (int wpc : {4, 8})
-          if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc, 0});
+          if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc, 0, 0});
       }
     hipEvent_t e0, e1;
     NFM_HIP(c, hipEventCreate(&e0));
@@ -1110,12 +1120,12 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     int nres = 0;
     nfm_status st = NFM_OK;
     // one untimed warm-up pass so that first-launch costs do not favour later candidates
-    st = muca_launches(c, c->sweeps, (uint64_t)std::min(calib_sweeps, 64), 0, kMaxSweepsPerLaunch, 0, 0, 0, 0);
+    st = muca_launches(c, c->sweeps, (uint64_t)std::min(calib_sweeps, 64), 0, kMaxSweepsPerLaunch, 0, 0, 0, 0, 0);
     for (size_t i = 0; i < cand.size() && st == NFM_OK; ++i) {
       const nfm_tuning& t = cand[i];
       if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, NFM_EDEVICE, "autotune: event"); break; }
       st = muca_launches(c, c->sweeps, (uint64_t)calib_sweeps, t.speculate, (uint32_t)t.sweeps_per_launch, t.schedule,
-                         t.waves_per_cu, t.hist, 0);
+                         t.waves_per_cu, t.hist, t.ws, 0);
       if (st != NFM_OK) break;
       float ms = 0.f;
       if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1143,7 +1153,7 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     if (cache_path) {
       std::ofstream f(cache_path, std::ios::app);
       if (f) f << key << " " << bt.speculate << " " << bt.sweeps_per_launch << " " << bt.schedule << " " << bt.waves_per_cu
-               << " " << bt.hist << "\n";
+               << " " << bt.hist << " " << bt.ws << "\n";
     }
     if (best) *best = bt;
     return nfm_set_tuning(c, &bt);

@@ -74,7 +74,7 @@ hipError_t launch_features(const RealInfo* reals, int n_real, const uint32_t* ja
 // (n_cu: compute units of the device; hist_mode: on-chip histogram 0 auto, 1 window, 2 every level,
 // 3 the table rows alone)
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
-                              int hist_mode, bool spec, hipStream_t s);
+                              int hist_mode, int ws_mode, bool spec, hipStream_t s);
 // persistent launch over all waves of the batch; order = wave indices, longest first
 hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uint32_t* counter, int grid, int n_cu,
                              int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s);
@@ -83,6 +83,8 @@ int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode)
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s);
 // the exchange thresholds of realization r as the sweep kernel computes them (inspection)
 hipError_t launch_pt_swap_table(const double* q, int r, int M, int D, uint32_t* swap, hipStream_t s);
+// name of the sweep kernel the last launch on this host thread used
+const char* last_sweep_kernel();
 bool sweep_supported(int L);
 
 }  // namespace nfm

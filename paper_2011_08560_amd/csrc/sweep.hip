@@ -13,6 +13,7 @@
 // bit operations (six flag strings and a bit-sliced adder). The attempts then run
 // one after the other, since each acceptance reads the walker's current energy.
 #include <algorithm>
+#include <cstdio>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -142,6 +143,29 @@ __device__ __forceinline__ int lds_load_i32(uint32_t byte_addr) {
 __device__ __forceinline__ void lds_store_i32(uint32_t byte_addr, int v) {
   *(__attribute__((address_space(3))) int*)(uintptr_t)byte_addr = v;
 }
+typedef uint32_t lds_v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 lds_load_u32x4(uint32_t byte_addr) {
+  const lds_v4u q = *(const __attribute__((address_space(3))) lds_v4u*)(uintptr_t)byte_addr;
+  return u32x4{{q.x, q.y, q.z, q.w}};
+}
+__device__ __forceinline__ void lds_store_u32x4(uint32_t byte_addr, const u32x4& w) {
+  const lds_v4u q = {w.v[0], w.v[1], w.v[2], w.v[3]};
+  *(__attribute__((address_space(3))) lds_v4u*)(uintptr_t)byte_addr = q;
+}
+
+// Warp-specialized form (expanded table only): a workgroup of two waves, the sampling wave and
+// a generator wave that computes the random words of the sampling wave's walkers two blocks
+// ahead into a ring of three block slots in LDS (16 bytes per walker and group of four sites),
+// after the sampling wave's table, couplings and histogram. Both waves meet at one barrier per
+// block. The generator's work leaves the sampling wave's instruction stream, and the two waves
+// share a SIMD's issue slots where one wave per SIMD would leave them idle.
+template <int L>
+__host__ __device__ constexpr uint32_t ws_slot_bytes() {
+  return (uint32_t)((Geo<L>::Q + 3) / 4) * 64u * 16u;
+}
+__host__ __device__ inline uint32_t ws_ring_base(int K, int jk_words_L, int hist_n) {
+  return ((uint32_t)K * 32u + 4u * (uint32_t)jk_words_L + 4u * (uint32_t)hist_n + 15u) & ~15u;
+}
 
 // Acceptance of one attempt and its effect on the state, as one instruction sequence: the
 // comparison r <= th' of the random word with the on-chip threshold (th' = thr - 1, or 0 for
@@ -254,7 +278,7 @@ __device__ __forceinline__ int clamp_row(int B, int Bmax) {
 // XT (multicanonical, no speculation): the table is expanded on chip to one row per level of
 // the realization (rows outside the stored range repeat its edge rows, as the clamp would), so
 // the row of a level is the level itself and the decision needs no clamp.
-template <int L, bool SPEC, bool PT, bool XT = false>
+template <int L, bool SPEC, bool PT, bool XT = false, bool WS = false>
 __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   using G = Geo<L>;
   using PW = typename G::PW;
@@ -262,9 +286,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   constexpr int NB = (G::BITS + 7) / 8;  // bytes of a plane-colour string
   constexpr int kZUnroll = L <= 6 ? L : 1;
   static_assert(!(PT && SPEC), "the tempering row does not depend on the decision");
-  static_assert(!(XT && (PT || SPEC)), "the expanded table is for the plain multicanonical form");
+  static_assert(!(XT && PT), "the expanded table is for the multicanonical form");
+  static_assert(!(XT && SPEC) || WS, "the speculative form with the expanded table runs beside a generator wave");
+  static_assert(!WS || XT, "the generator wave serves the expanded-table form");
+  const int lane = (int)(threadIdx.x & 63u);
   const int r = A.wave_real[wave];
-  const int wl = A.wave_wl[wave] + (int)threadIdx.x;
+  const int wl = A.wave_wl[wave] + lane;
   const RealInfo& RI = A.reals[r];
   const int e_base = RI.e_base, walkers = RI.walkers, K = RI.K;
   const int row0 = (PT || XT) ? 0 : RI.row0, rows = PT ? A.pt_M : (XT ? K : RI.rows);
@@ -288,7 +315,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   const int hlo = max(0, row0 - A.hist_margin), hn = A.hist_n;
   {
     const uint32_t* gt = A.tables + RI.table_off;
-    for (int e = threadIdx.x; e < rows * 8; e += 64) {
+    for (int e = lane; e < rows * 8; e += 64) {
       const int jj = e & 7;
       const int u = jj < 4 ? 3 - jj : (jj == 4 ? 7 : 11 - jj);
       int gr = e >> 3;   // row of the stored table
@@ -298,12 +325,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       *(__attribute__((address_space(3))) uint32_t*)(uintptr_t)(e * 4) = vp;
     }
     const uint32_t* jg = A.jk + RI.jk_off;
-    for (int e = threadIdx.x; e < jk_words(L); e += 64) lds_store_i32(jbase + 4u * (uint32_t)e, (int)jg[e]);
+    for (int e = lane; e < jk_words(L); e += 64) lds_store_i32(jbase + 4u * (uint32_t)e, (int)jg[e]);
   }
   if constexpr (PT) {
-    lds_store_i32(sAcc + 4u * threadIdx.x, 0);
+    lds_store_i32(sAcc + 4u * (uint32_t)lane, 0);
   } else {
-    for (int e = threadIdx.x; e < hn; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
+    for (int e = lane; e < hn; e += 64) lds_store_i32(hbase + 4u * (uint32_t)e, 0);
   }
   __syncthreads();
 
@@ -328,7 +355,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   uint32_t pt_base = 0, pt_set = 0;
   bool pt_active = false;
   if constexpr (PT) {
-    const uint32_t sw = __umulhi(threadIdx.x, A.pt_minv);
+    const uint32_t sw = __umulhi((uint32_t)lane, A.pt_minv);
     pt_active = sw < (uint32_t)A.pt_spw;
     pt_base = sw * (uint32_t)A.pt_M;
     pt_set = (uint32_t)(A.wave_wl[wave] >> 6) * (uint32_t)A.pt_spw + sw;
@@ -371,8 +398,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
 
   const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
   // Round keys in VGPRs: uniform values, but keeping them out of the scalar file leaves room for
-  // the per-plane coupling words and constants without spilling scalar registers.
-  PhiloxKeysV kv = philox_round_keys_v(key0, key1);
+  // the per-plane coupling words and constants without spilling scalar registers. (Not needed
+  // when a generator wave supplies the words.)
+  PhiloxKeysV kv;
+  if constexpr (!WS) kv = philox_round_keys_v(key0, key1);
   const uint32_t ctr3 = ((uint32_t)wl << 8) | (PT ? kTagPT : kTagAcc);
 
   // Level steps of the sites of block (c, z), a plane-colour string, from the other colour's
@@ -464,8 +493,20 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   // The generator runs one group ahead: pr holds the words of the next group of four sites, and
   // its rounds are spread over the attempts of the group before it (also across blocks, colours
   // and sweeps), so that they fill the wait for each threshold read.
-  PhiloxRun pr = group_ctr(0, 0, 0, A.t0);
-  philox_rounds<0, 10>(pr, kv);
+  PhiloxRun pr{};
+  if constexpr (!WS) {
+    pr = group_ctr(0, 0, 0, A.t0);
+    philox_rounds<0, 10>(pr, kv);
+  }
+  // Warp-specialized form: the words of block b sit in ring slot b mod 3; rw holds the next
+  // group's words, read one group ahead.
+  const uint32_t rbase = WS ? ws_ring_base(K, jk_words(L), hn) : 0u;
+  auto ring = [&](uint32_t slot, int g) __attribute__((always_inline)) -> uint32_t {
+    return rbase + slot * ws_slot_bytes<L>() + (uint32_t)(g * 64 + lane) * 16u;
+  };
+  uint32_t rslot = 0, rslot_n = 1;
+  u32x4 rw{};
+  if constexpr (WS) rw = lds_load_u32x4(ring(0, 0));
 
   for (uint32_t s = 0; s < A.n_sweeps; ++s) {
     const uint64_t t = A.t0 + s;
@@ -504,12 +545,20 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
         }
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-          const u32x4 rnd = {{pr.c0, pr.c1, pr.c2, pr.c3}};
-          // the next group: in this block, the next block, the other colour or the next sweep
-          if (g + 1 < NG) pr = group_ctr(c, z, g + 1, t);
-          else if (has_next) pr = group_ctr(c, z + 1, 0, t);
-          else if (c == 0) pr = group_ctr(1, 0, 0, t);
-          else pr = group_ctr(0, 0, 0, t + 1);
+          u32x4 rnd;
+          if constexpr (WS) {
+            // this group's words, and the read of the next group's (in this block, or the first
+            // group of the next block, whose slot the generator filled before the last barrier)
+            rnd = rw;
+            rw = lds_load_u32x4(g + 1 < NG ? ring(rslot, g + 1) : ring(rslot_n, 0));
+          } else {
+            rnd = u32x4{{pr.c0, pr.c1, pr.c2, pr.c3}};
+            // the next group: in this block, the next block, the other colour or the next sweep
+            if (g + 1 < NG) pr = group_ctr(c, z, g + 1, t);
+            else if (has_next) pr = group_ctr(c, z + 1, 0, t);
+            else if (c == 0) pr = group_ctr(1, 0, 0, t);
+            else pr = group_ctr(0, 0, 0, t + 1);
+          }
           const int n_att = (4 * g + 4 <= Q) ? 4 : Q - 4 * g;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -519,14 +568,16 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
             const int p = y * FB + j, w = p >> 5;
             if constexpr (SPEC && !PT) {
               const uint32_t rc = rnd.v[i];
-              if (i == 0) philox_rounds<0, 3>(pr, kv);
-              if (i == 1) philox_rounds<3, 5>(pr, kv);
-              if (i == 2) philox_rounds<5, 8>(pr, kv);
-              if (i == 3) philox_rounds<8, 10>(pr, kv);
+              if constexpr (!WS) {
+                if (i == 0) philox_rounds<0, 3>(pr, kv);
+                if (i == 1) philox_rounds<3, 5>(pr, kv);
+                if (i == 2) philox_rounds<5, 8>(pr, kv);
+                if (i == 3) philox_rounds<8, 10>(pr, kv);
+              }
               // thresholds of site q+1 for both outcomes of q are loaded before q is decided; the
               // threshold of site q is picked from the pair loaded one site earlier
               const int Bacc = B + __builtin_amdgcn_sbfe((int)hi_cur, 2, 3) * 32;
-              const int Racc = clamp_row(Bacc, Bmax);
+              const int Racc = XT ? Bacc : clamp_row(Bacc, Bmax);
               uint32_t hi_next = 0, n_rej = 0, n_acc = 0;
               if (q + 1 < Q) {
                 hi_next = gather(Vc, q + 1);
@@ -555,13 +606,15 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
               //     rounds' outputs pass through the second one. The first takes only the words
               //     the round's products do not read: a VALU read of a register an asm statement
               //     wrote costs a wait state, and uniform words stay scalar.
-              asm volatile("" : "+v"(pr.c1), "+v"(pr.c3));
-              if (i == 0) philox_rounds<0, 3>(pr, kv);
-              if (i == 1) philox_rounds<3, 5>(pr, kv);
-              if (i == 2) philox_rounds<5, 8>(pr, kv);
-              if (i == 3) philox_rounds<8, 10>(pr, kv);
+              if constexpr (!WS) {
+                asm volatile("" : "+v"(pr.c1), "+v"(pr.c3));
+                if (i == 0) philox_rounds<0, 3>(pr, kv);
+                if (i == 1) philox_rounds<3, 5>(pr, kv);
+                if (i == 2) philox_rounds<5, 8>(pr, kv);
+                if (i == 3) philox_rounds<8, 10>(pr, kv);
+              }
               const uint32_t rc = rnd.v[i];
-              asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
+              if constexpr (!WS) asm volatile("" : "+v"(pr.c0), "+v"(pr.c1), "+v"(pr.c2), "+v"(pr.c3));
               // (3) the decision, the next site's table address and (multicanonical) its read,
               //     issued before the bookkeeping and flips that follow
               if constexpr (PT) {
@@ -590,9 +643,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
             }
           }
           // a short last group: the generator rounds its missing attempts would have run
-          if (n_att == 1) philox_rounds<3, 10>(pr, kv);
-          if (n_att == 2) philox_rounds<5, 10>(pr, kv);
-          if (n_att == 3) philox_rounds<8, 10>(pr, kv);
+          if constexpr (!WS) {
+            if (n_att == 1) philox_rounds<3, 10>(pr, kv);
+            if (n_att == 2) philox_rounds<5, 10>(pr, kv);
+            if (n_att == 3) philox_rounds<8, 10>(pr, kv);
+          }
           if constexpr (!PT) {
             // Every second group (and at the block's end): did an attempt since the last check
             // leave the window? Then replay those attempts' bookkeeping exactly.
@@ -619,6 +674,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
         }
 #pragma unroll
         for (int w = 0; w < NWP; ++w) lat(c, w)[z] = Cw[w];
+        if constexpr (WS) {
+          // this block's words are consumed: the generator may refill their slot
+          __syncthreads();
+          rslot = rslot_n;
+          rslot_n = rslot_n == 2u ? 0u : rslot_n + 1u;
+        }
         if (has_next) {
 #pragma unroll
           for (int k = 0; k < NB; ++k) Vc[k] = Vn[k];
@@ -697,14 +758,14 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     A.pt_slot[gw] = slot;
     // exchange counters of the pairs (s, s+1) of this lane's set, s = lane index in the set
     const int M = A.pt_M;
-    const int cidx = (int)(threadIdx.x - pt_base);
+    const int cidx = (int)((uint32_t)lane - pt_base);
     if (pt_active && cidx < M - 1)   // global set index: walker offsets of realizations are multiples of 64
       A.pt_acc[(int64_t)(RI.walker_off / 64 * A.pt_spw + pt_set) * (M - 1) + cidx] +=
-          (uint64_t)lds_load_i32(sAcc + 4u * threadIdx.x);
+          (uint64_t)lds_load_i32(sAcc + 4u * (uint32_t)lane);
   } else {
     // the launch's histogram counts (at most 64 walkers x 2^20 sweeps per level)
     __syncthreads();
-    for (int e = threadIdx.x; e < hn; e += 64) {
+    for (int e = lane; e < hn; e += 64) {
       const uint32_t c = (uint32_t)lds_load_i32(hbase + 4u * (uint32_t)e);
       if (c) atomicAdd(A.hist + RI.level_off + hlo + e, (unsigned long long)c);   // c > 0: hlo + e < K
     }
@@ -715,6 +776,68 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
     A.ws.rt_count[gw] += tr.trips;
     A.ws.t_first[gw] = tr.t_first;
     A.ws.t_last[gw] = tr.t_last;
+  }
+}
+
+// The generator wave of the warp-specialized form: the words of every group of every block of
+// the launch (blocks in sweep order: sweep, colour, plane), two blocks ahead of the sampling
+// wave. It meets the sampling wave at the same barriers: after the tables are staged, at the end
+// of every block, before the histogram flush.
+template <int L>
+__device__ __forceinline__ void generate_words(const SweepArgs& A, int wave) {
+  constexpr int Q = Geo<L>::Q, NG = (Q + 3) / 4;
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  const int lane = (int)(threadIdx.x & 63u);
+  const RealInfo& RI = A.reals[A.wave_real[wave]];
+  const uint32_t ctr3 = ((uint32_t)(A.wave_wl[wave] + lane) << 8) | kTagAcc, real_id = RI.real_id;
+  const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
+  const uint32_t rbase = ws_ring_base(RI.K, jk_words(L), A.hist_n);
+  const int64_t nb = (int64_t)A.n_sweeps * 2 * L;
+  auto fill = [&](int64_t b, uint32_t slot) __attribute__((always_inline)) {
+    if (b >= nb) return;
+    const uint32_t t = (uint32_t)(A.t0 + (uint64_t)(b / (2 * L)));
+    const uint32_t cz = (uint32_t)(b % (2 * L));   // c L + z
+    for (int g = 0; g < NG; ++g) {
+      // counter words 0..2 are uniform: the first rounds' uniform products stay scalar
+      uint32_t c0 = (cz << 8) | (uint32_t)g, c1 = t, c2 = real_id, c3 = ctr3, k0 = key0, k1 = key1;
+#pragma unroll
+      for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += W0;
+        k1 += W1;
+      }
+      lds_store_u32x4(rbase + slot * ws_slot_bytes<L>() + (uint32_t)(g * 64 + lane) * 16u, u32x4{{c0, c1, c2, c3}});
+    }
+  };
+  fill(0, 0u);
+  fill(1, 1u);
+  __syncthreads();   // tables staged, blocks 0 and 1 written
+  uint32_t slot = 2;
+  for (int64_t b = 0; b < nb; ++b) {
+    fill(b + 2, slot);
+    slot = slot == 2u ? 0u : slot + 1u;
+    __syncthreads();   // the sampling wave has finished block b
+  }
+  __syncthreads();     // before the sampling wave's histogram flush
+}
+
+template <int L, bool SPEC>
+__global__ void __launch_bounds__(128) k_sweeps_ws(SweepArgs A) {
+  extern __shared__ uint32_t stab[];  // addressed from LDS address 0
+  (void)stab;
+  // the role is uniform per wave: a scalar branch, so that each wave meets only its own barriers
+  const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (role == 0) {
+    // the sampling wave's decisions form the critical chain: its instructions go first
+    __builtin_amdgcn_s_setprio(3);
+    sweep_wave<L, SPEC, false, true, true>(A, (int)blockIdx.x);
+  } else {
+    generate_words<L>(A, (int)blockIdx.x);
   }
 }
 
@@ -772,6 +895,11 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Name of the sweep kernel the last launch on this host thread used (for reports).
+static thread_local char g_last_kernel[48] = "none";
+const char* last_sweep_kernel() { return g_last_kernel; }
+static void note_kernel(const char* form, int L) { snprintf(g_last_kernel, sizeof(g_last_kernel), "%s<%d>", form, L); }
+
 template <int L, bool SPEC, bool PT, bool XT = false>
 static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, hipStream_t s) {
   // The kernel addresses its dynamic LDS block from address 0, which is only valid
@@ -784,6 +912,7 @@ static hipError_t launch_LS(const SweepArgs& a, int n_waves, size_t lds_bytes, h
     if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     checked = 1;
   }
+  note_kernel(PT ? "k_sweeps_pt" : SPEC ? "k_sweeps_spec" : XT ? "k_sweeps_xt" : "k_sweeps", L);
   hipLaunchKernelGGL((k_sweeps<L, SPEC, PT, XT>), dim3(n_waves), dim3(64), lds_bytes, s, a);
   return hipGetLastError();
 }
@@ -813,25 +942,58 @@ static HistPlan plan_hist(const void* f, size_t base_lds, int rows, int K, int w
   return occ_full >= std::min(occ_win, want_blocks) ? full : win;
 }
 
+template <int L, bool SPEC>
+static hipError_t launch_ws(const SweepArgs& a, int n_waves, size_t lds_bytes, hipStream_t s) {
+  static int checked = 0;
+  if (!checked) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps_ws<L, SPEC>));
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+    checked = 1;
+  }
+  note_kernel(SPEC ? "k_sweeps_ws_spec" : "k_sweeps_ws", L);
+  hipLaunchKernelGGL((k_sweeps_ws<L, SPEC>), dim3(n_waves), dim3(128), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+// ws_mode (expanded-table launches): 0 automatic -- the generator wave when the launch has at
+// most one wave of walkers per SIMD (4 per CU) and all its workgroups stay resident -- 1 never,
+// 2 always (when the expanded table is used).
 template <int L>
-static hipError_t launch_L(SweepArgs a, int n_waves, int lds_rows, int hist_levels, int n_cu, int hist_mode, bool spec,
-                           bool pt, hipStream_t s) {
+static hipError_t launch_L(SweepArgs a, int n_waves, int lds_rows, int hist_levels, int n_cu, int hist_mode,
+                           int ws_mode, bool spec, bool pt, hipStream_t s) {
   const size_t jb = (size_t)jk_words(L) * 4;
   if (pt) return launch_LS<L, false, true>(a, n_waves, (size_t)a.pt_M * 32 + 3 * 256 + jb, s);
   const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps<L, true, false, false>)
                        : reinterpret_cast<const void*>(&k_sweeps<L, false, false, false>);
   const int want = (n_waves + n_cu - 1) / std::max(n_cu, 1);
   const HistPlan h = plan_hist(f, (size_t)lds_rows * 32 + jb, lds_rows, hist_levels, want, hist_mode);   // table, couplings
-  if (!spec && hist_mode == 0) {
+  if (hist_mode == 0) {
     // the expanded table (and every level of the histogram) when it costs no resident workgroups
     const void* fx = reinterpret_cast<const void*>(&k_sweeps<L, false, false, true>);
     const size_t lds_x = (size_t)hist_levels * 32 + jb + (size_t)hist_levels * 4;
     int occ_x = 0, occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_x, fx, 64, lds_x) == hipSuccess &&
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 64, h.lds) == hipSuccess && occ_x >= std::min(occ, want)) {
-      a.hist_margin = hist_levels;
-      a.hist_n = hist_levels;
-      return launch_LS<L, false, false, true>(a, n_waves, lds_x, s);
+      if (ws_mode != 1) {
+        const size_t lds_w = (size_t)ws_ring_base(hist_levels, jk_words(L), hist_levels) + 3 * (size_t)ws_slot_bytes<L>();
+        const void* fw = spec ? reinterpret_cast<const void*>(&k_sweeps_ws<L, true>)
+                              : reinterpret_cast<const void*>(&k_sweeps_ws<L, false>);
+        int occ_w = 0;
+        const bool fits = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_w, fw, 128, lds_w) == hipSuccess &&
+                          occ_w >= want;
+        if (ws_mode == 2 ? occ_w >= 1 : (fits && n_waves <= 4 * n_cu)) {
+          a.hist_margin = hist_levels;
+          a.hist_n = hist_levels;
+          return spec ? launch_ws<L, true>(a, n_waves, lds_w, s) : launch_ws<L, false>(a, n_waves, lds_w, s);
+        }
+      }
+      if (!spec) {
+        a.hist_margin = hist_levels;
+        a.hist_n = hist_levels;
+        return launch_LS<L, false, false, true>(a, n_waves, lds_x, s);
+      }
     }
   }
   a.hist_margin = h.margin;
@@ -840,14 +1002,14 @@ static hipError_t launch_L(SweepArgs a, int n_waves, int lds_rows, int hist_leve
 }
 
 static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
-                             int hist_mode, bool spec, bool pt, hipStream_t s) {
+                             int hist_mode, int ws_mode, bool spec, bool pt, hipStream_t s) {
   switch (L) {
-    case 2: return launch_L<2>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
-    case 4: return launch_L<4>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
-    case 6: return launch_L<6>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
-    case 8: return launch_L<8>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
-    case 10: return launch_L<10>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
-    case 12: return launch_L<12>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, pt, s);
+    case 2: return launch_L<2>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, pt, s);
+    case 4: return launch_L<4>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, pt, s);
+    case 6: return launch_L<6>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, pt, s);
+    case 8: return launch_L<8>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, pt, s);
+    case 10: return launch_L<10>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, pt, s);
+    case 12: return launch_L<12>(a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, pt, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -855,8 +1017,8 @@ static hipError_t launch_any(int L, const SweepArgs& a, int n_waves, int lds_row
 bool sweep_supported(int L) { return L >= 2 && L <= kMaxL && (L % 2) == 0; }
 
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
-                              int hist_mode, bool spec, hipStream_t s) {
-  return launch_any(L, a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, spec, false, s);
+                              int hist_mode, int ws_mode, bool spec, hipStream_t s) {
+  return launch_any(L, a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, false, s);
 }
 
 template <bool SPEC>
@@ -873,6 +1035,7 @@ static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  snprintf(g_last_kernel, sizeof(g_last_kernel), "%s", SPEC ? "k_sweeps_queue_spec" : "k_sweeps_queue");
   hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), lds_bytes, s, a, order, n_items, counter);
   return hipGetLastError();
 }
@@ -908,7 +1071,7 @@ hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t 
   if (a.pt_M < 2 || a.pt_M > kMaxReplicas || a.pt_spw != 64 / a.pt_M ||
       a.pt_minv != 0xFFFFFFFFu / (uint32_t)a.pt_M + 1u)
     return hipErrorInvalidValue;
-  return launch_any(L, a, n_waves, 1, 0, 1, 0, false, true, s);
+  return launch_any(L, a, n_waves, 1, 0, 1, 0, 1, false, true, s);
 }
 
 }  // namespace nfm

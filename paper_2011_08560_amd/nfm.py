@@ -45,8 +45,8 @@ WL_DTYPE = np.dtype([("ln_f", np.float64), ("flatness", np.float64), ("stage", n
 RT_SUMMARY_DTYPE = np.dtype([("tau_pop", np.float64), ("trips", np.uint64), ("n_used", np.int32),
                              ("n_censored", np.int32)], align=True)
 PROFILE_FLAT, PROFILE_POWER, PROFILE_INVK = 0, 1, 2
-TUNING_FIELDS = ("speculate", "sweeps_per_launch", "schedule", "waves_per_cu", "hist")
-TUNE_RESULT_DTYPE = np.dtype([("tuning", np.int32, (5,)), ("attempts_per_s", np.float64)], align=True)
+TUNING_FIELDS = ("speculate", "sweeps_per_launch", "schedule", "waves_per_cu", "hist", "ws")
+TUNE_RESULT_DTYPE = np.dtype([("tuning", np.int32, (6,)), ("attempts_per_s", np.float64)], align=True)
 
 class Frechet(C.Structure):
     """nfm_frechet: parameters (mu, beta, xi) of Eq. (9)."""
@@ -108,6 +108,7 @@ def lib():
         "nfm_reset_trace": (i32, [vp]),
         "nfm_sync": (i32, [vp]),
         "nfm_checkpoint_bytes": (i32, [vp, C.POINTER(sz)]),
+        "nfm_last_kernel": (C.c_char_p, [vp]),
         "nfm_checkpoint": (i32, [vp, vp, sz]),
         "nfm_restore": (i32, [vp, vp, sz]),
         "nfm_set_histograms": (i32, [vp, vp]),
@@ -404,6 +405,10 @@ class Batch:
     def sync(self):
         self._check(self._lib.nfm_sync(self.ctx), "sync")
 
+    def last_kernel(self) -> str:
+        """The sweep kernel form the last launch used (nfm_last_kernel)."""
+        return self._lib.nfm_last_kernel(self.ctx).decode()
+
     def checkpoint(self) -> np.ndarray:
         """The whole state of the context as a host byte array (nfm_checkpoint)."""
         n = C.c_size_t()
@@ -493,12 +498,12 @@ class Batch:
 
     # launch tuning
     def set_tuning(self, speculate: int = -1, sweeps_per_launch: int = 0, schedule: int = 0, waves_per_cu: int = 0,
-                   hist: int = 0):
-        t = np.array([speculate, sweeps_per_launch, schedule, waves_per_cu, hist], np.int32)
+                   hist: int = 0, ws: int = 0):
+        t = np.array([speculate, sweeps_per_launch, schedule, waves_per_cu, hist, ws], np.int32)
         self._check(self._lib.nfm_set_tuning(self.ctx, t.ctypes.data), "set_tuning")
 
     def get_tuning(self) -> dict:
-        t = np.zeros(5, np.int32)
+        t = np.zeros(len(TUNING_FIELDS), np.int32)
         self._check(self._lib.nfm_get_tuning(self.ctx, t.ctypes.data), "get_tuning")
         return dict(zip(TUNING_FIELDS, (int(x) for x in t)))
 
@@ -507,7 +512,7 @@ class Batch:
         apply the fastest. Returns (best tuning dict, list of (tuning dict, attempts/s))."""
         res = np.zeros(max_results, TUNE_RESULT_DTYPE)
         n = C.c_int32()
-        best = np.zeros(5, np.int32)
+        best = np.zeros(len(TUNING_FIELDS), np.int32)
         path = cache_path.encode() if cache_path else None
         self._check(self._lib.nfm_autotune(self.ctx, calib_sweeps, path, res.ctypes.data if max_results else None,
                                            max_results, C.byref(n), best.ctypes.data), "autotune")

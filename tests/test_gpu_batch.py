@@ -72,12 +72,14 @@ def test_spins_roundtrip_across_sizes(nfm, orc):
 
 
 # hist: 0 automatic, 1 window, 2 every level, 3 the table rows alone (most counts outside LDS)
-CONFIGS = [dict(schedule=1, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0),
-           dict(schedule=1, speculate=1, sweeps_per_launch=7, waves_per_cu=0, hist=1),
-           dict(schedule=1, speculate=0, sweeps_per_launch=16, waves_per_cu=1, hist=3),
-           dict(schedule=1, speculate=1, sweeps_per_launch=0, waves_per_cu=3, hist=2),
-           dict(schedule=0, speculate=1, sweeps_per_launch=9, waves_per_cu=0, hist=3),
-           dict(schedule=0, speculate=0, sweeps_per_launch=11, waves_per_cu=0, hist=1)]
+CONFIGS = [dict(schedule=1, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0, ws=0),
+           dict(schedule=1, speculate=1, sweeps_per_launch=7, waves_per_cu=0, hist=1, ws=0),
+           dict(schedule=1, speculate=0, sweeps_per_launch=16, waves_per_cu=1, hist=3, ws=0),
+           dict(schedule=1, speculate=1, sweeps_per_launch=0, waves_per_cu=3, hist=2, ws=0),
+           dict(schedule=0, speculate=1, sweeps_per_launch=9, waves_per_cu=0, hist=3, ws=0),
+           dict(schedule=0, speculate=0, sweeps_per_launch=11, waves_per_cu=0, hist=1, ws=0),
+           dict(schedule=0, speculate=0, sweeps_per_launch=13, waves_per_cu=0, hist=0, ws=2),
+           dict(schedule=0, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0, ws=1)]
 
 
 def test_schedules_give_identical_results(nfm, orc):
@@ -137,7 +139,7 @@ def test_autotune_restores_state_and_caches(nfm, orc, tmp_path):
     _same(_state(b), before)
     assert b.sweep_counter == t_before
     text = open(cache).read().split()
-    assert len(text) == 6 and [int(x) for x in text[1:]] == [best[k] for k in nfm.TUNING_FIELDS]
+    assert len(text) == 7 and [int(x) for x in text[1:]] == [best[k] for k in nfm.TUNING_FIELDS]
     best2, table2 = b.autotune(calib_sweeps=32, cache_path=cache)    # cached: no measurement
     assert best2 == best and table2 == []
     b.run_sweeps(20)

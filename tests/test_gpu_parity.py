@@ -81,12 +81,15 @@ def _weights(orc, L, J, beta, noise, seed):
     return K, eb, lnw, k_lo, k_top
 
 
-@pytest.mark.parametrize("spec", [0, 1])
+# plain and speculative forms, each without (ws=1: expanded table / compact table) and with (ws=2,
+# expanded table) the generator wave
+@pytest.mark.parametrize("spec,ws", [(0, 1), (0, 2), (1, 1), (1, 2)])
 @pytest.mark.parametrize("L,T", [(2, 40), (4, 32), (6, 24), (8, 16), (10, 10), (12, 8)])
-def test_sweeps_bit_exact(nfm, orc, L, T, spec):
+def test_sweeps_bit_exact(nfm, orc, L, T, spec, ws):
     n_real, W, rid0 = 2, 64, 3
+    print("sweeps bit-exact: L", L, "sweeps", T, "speculate", spec, "ws", ws, flush=True)
     b = nfm.Batch([L] * n_real, [W] * n_real, DSEED, WSEED, first_real_id=rid0, trace_capacity=T)
-    b.set_tuning(speculate=spec, sweeps_per_launch=5)   # several launches per run: resume inside
+    b.set_tuning(speculate=spec, sweeps_per_launch=5, ws=ws)   # several launches per run: resume inside
     b.init_couplings()
     b.init_spins()
     b.compute_energies()
