@@ -803,7 +803,13 @@ __device__ __forceinline__ void generate_words(const SweepArgs& A, int wave) {
 #pragma unroll
       for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // Which words vary across the wave: only c3 at the start; rounds 0-2 each xor at most
+        // one varying word into uniform ones (a scalar xor and one vector xor), from round 3 on
+        // (c2's side) and round 4 on (c0's side) two varying words meet: one three-input v_bitop3.
+        const uint32_t n0 = round >= 4 ? __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96)
+                                       : (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = round >= 3 ? __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96)
+                                       : (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
