@@ -42,6 +42,37 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
   return r;
 }
 
+// The same generator for counters whose words 0..2 are uniform across the wave and word 3
+// varies (the acceptance and tempering streams): rounds 0-2 xor at most one varying word into
+// uniform ones (a scalar xor, then one vector xor) and leave the uniform products to the scalar
+// unit; from round 3 (c2's side) and round 4 (c0's side) on two varying words meet, one
+// three-input v_bitop3. The keys stay uniform.
+__device__ __forceinline__ u32x4 philox4x32_10_u(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    const uint32_t n0 = round >= 4 ? __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96)
+                                   : (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = round >= 3 ? __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96)
+                                   : (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += W0;
+    k1 += W1;
+  }
+  u32x4 r;
+  r.v[0] = c0;
+  r.v[1] = c1;
+  r.v[2] = c2;
+  r.v[3] = c3;
+  return r;
+}
+
 // The same generator with the ten round keys precomputed in vector registers.
 struct PhiloxKeysV {
   uint32_t k0[10], k1[10];

@@ -786,7 +786,6 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
 template <int L>
 __device__ __forceinline__ void generate_words(const SweepArgs& A, int wave) {
   constexpr int Q = Geo<L>::Q, NG = (Q + 3) / 4;
-  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
   const int lane = (int)(threadIdx.x & 63u);
   const RealInfo& RI = A.reals[A.wave_real[wave]];
   const uint32_t ctr3 = ((uint32_t)(A.wave_wl[wave] + lane) << 8) | kTagAcc, real_id = RI.real_id;
@@ -798,26 +797,8 @@ __device__ __forceinline__ void generate_words(const SweepArgs& A, int wave) {
     const uint32_t t = (uint32_t)(A.t0 + (uint64_t)(b / (2 * L)));
     const uint32_t cz = (uint32_t)(b % (2 * L));   // c L + z
     for (int g = 0; g < NG; ++g) {
-      // counter words 0..2 are uniform: the first rounds' uniform products stay scalar
-      uint32_t c0 = (cz << 8) | (uint32_t)g, c1 = t, c2 = real_id, c3 = ctr3, k0 = key0, k1 = key1;
-#pragma unroll
-      for (int round = 0; round < 10; ++round) {
-        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
-        // Which words vary across the wave: only c3 at the start; rounds 0-2 each xor at most
-        // one varying word into uniform ones (a scalar xor and one vector xor), from round 3 on
-        // (c2's side) and round 4 on (c0's side) two varying words meet: one three-input v_bitop3.
-        const uint32_t n0 = round >= 4 ? __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96)
-                                       : (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = round >= 3 ? __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96)
-                                       : (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += W0;
-        k1 += W1;
-      }
-      lds_store_u32x4(rbase + slot * ws_slot_bytes<L>() + (uint32_t)(g * 64 + lane) * 16u, u32x4{{c0, c1, c2, c3}});
+      const u32x4 w = philox4x32_10_u((cz << 8) | (uint32_t)g, t, real_id, ctr3, key0, key1);
+      lds_store_u32x4(rbase + slot * ws_slot_bytes<L>() + (uint32_t)(g * 64 + lane) * 16u, w);
     }
   };
   fill(0, 0u);
