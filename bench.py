@@ -27,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic integer lane-operations per spin-flip attempt:
+# Algorithmic integer lane-operations per spin-flip attempt (the word-parallel sweep's floor):
 # Philox4x32-10 share 10 (2.5 rounds x (2 wide products + 2 three-input xors)), neighbour
 # count 1, table address 2, acceptance 2, spin/energy update 2, bookkeeping check 1.
 ALG_OPS_PER_ATTEMPT = 18.0
