@@ -111,6 +111,8 @@ def test_sweeps_bit_exact(nfm, orc, L, T, spec, ws):
     # two launches: resuming must not change anything
     b.run_sweeps(T // 2)
     b.run_sweeps(T - T // 2)
+    form = {(0, 1): "k_sweeps_xt", (0, 2): "k_sweeps_ws", (1, 1): "k_sweeps_spec", (1, 2): "k_sweeps_ws_spec"}
+    assert b.last_kernel() == f"{form[(spec, ws)]}<{L}>"   # the form under test is the one that ran
     ws = b.read_walkers()
     H = b.read_histograms()
     trace = b.read_trace()
