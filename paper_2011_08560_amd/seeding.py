@@ -146,7 +146,7 @@ def generate(Ls, n_per_L, n_sweeps, f_tol, n_max, chunk=4096, first_id=0, log=No
             n = min(chunk, n_per_L - done)
             b = make_batch([L] * n, first_real_id=rid)
             x = canonical_features(b)
-            first = iterate(b, n_sweeps, f_tol, n_max)
+            first = iterate(b, n_sweeps, f_tol, n_max, log=log)
             y, m, ok = converged_targets(b, first, n_max)
             xs.append(x)
             ys.append(y)
@@ -170,7 +170,7 @@ def infer(mlp, x):
     return out
 
 
-def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID):
+def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID, log=None):
     """Paired comparison on fresh realizations: the same seeds, the same canonical run, then the
     plain start against the seeded one. Returns the rounds to converge of both arms."""
     plain = make_batch([L] * n_real, first_real_id=first_id)
@@ -181,8 +181,8 @@ def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID):
     curves = infer(mlp, x)
     seeded.rec_init(0, 1.0, 0.0)
     k_seed = seeded.rec_seed_grid(curves)
-    it_plain = iterate(plain, n_sweeps, f_tol, n_max)
-    it_seed = iterate(seeded, n_sweeps, f_tol, n_max, initialized=True)
+    it_plain = iterate(plain, n_sweeps, f_tol, n_max, log=log)
+    it_seed = iterate(seeded, n_sweeps, f_tol, n_max, initialized=True, log=log)
     plain.close()
     seeded.close()
     return it_plain, it_seed, k_seed
@@ -217,7 +217,7 @@ def main(argv=None):
     mlp = nfm.Mlp(batch_max=256)
     mlp.init(args.seed)
     losses, val = train(mlp, x, y, m, epochs=args.epochs, lr=args.lr, seed=args.seed, log=log)
-    it_p, it_s, ks = evaluate(mlp, args.eval_L, args.eval_real, args.sweeps, args.f_tol, args.n_max)
+    it_p, it_s, ks = evaluate(mlp, args.eval_L, args.eval_real, args.sweeps, args.f_tol, args.n_max, log=log)
     out = {"train": {"L": args.train_L, "per_L": stats, "final_loss": losses[-1], "val_loss": val},
            "eval": {"L": args.eval_L, "realizations": args.eval_real,
                     **summary(it_p, it_s, ks, args.n_max)},
