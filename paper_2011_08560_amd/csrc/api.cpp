@@ -719,6 +719,7 @@ nfm_status nfm_sync(nfm_ctx* c) {
 // holds offsets, not addresses, so the copy is valid at any workspace address).
 namespace {
 constexpr char kCkptMagic[8] = {'N', 'F', 'M', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkptVersion = 2;   // 2: the tuning's generator-wave mode is part of the header
 struct CkptHeader {
   char magic[8];
   uint32_t version, n_real;
@@ -763,7 +764,7 @@ nfm_status nfm_checkpoint(nfm_ctx* c, void* host_blob, size_t capacity) {
   if (capacity < ckpt_bytes(c)) return fail(c, NFM_ESIZE, "checkpoint: buffer smaller than nfm_checkpoint_bytes()");
   CkptHeader h{};
   std::memcpy(h.magic, kCkptMagic, 8);
-  h.version = 1;
+  h.version = kCkptVersion;
   h.n_real = (uint32_t)c->n_real;
   h.disorder_seed = c->disorder_seed;
   h.walker_seed = c->walker_seed;
@@ -800,7 +801,7 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
   if (!host_blob || size < sizeof(CkptHeader)) return fail(c, NFM_EINVAL, "restore: no checkpoint");
   CkptHeader h;
   std::memcpy(&h, host_blob, sizeof(h));
-  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion)
     return fail(c, NFM_EINVAL, "restore: not a checkpoint of this library version");
   if (h.n_real != (uint32_t)c->n_real || h.batch_hash != batch_hash(c) || h.workspace_bytes != c->lay.total ||
       h.disorder_seed != c->disorder_seed || h.walker_seed != c->walker_seed || h.trace_cap != c->trace_cap)
