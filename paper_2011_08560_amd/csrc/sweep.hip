@@ -791,22 +791,30 @@ __device__ __forceinline__ void generate_words(const SweepArgs& A, int wave) {
   const uint32_t ctr3 = ((uint32_t)(A.wave_wl[wave] + lane) << 8) | kTagAcc, real_id = RI.real_id;
   const uint32_t key0 = (uint32_t)A.walker_seed, key1 = (uint32_t)(A.walker_seed >> 32);
   const uint32_t rbase = ws_ring_base(RI.K, jk_words(L), A.hist_n);
-  const int64_t nb = (int64_t)A.n_sweeps * 2 * L;
-  auto fill = [&](int64_t b, uint32_t slot) __attribute__((always_inline)) {
-    if (b >= nb) return;
-    const uint32_t t = (uint32_t)(A.t0 + (uint64_t)(b / (2 * L)));
-    const uint32_t cz = (uint32_t)(b % (2 * L));   // c L + z
+  // blocks in the sampling wave's order; (t, cz = c L + z) names the block to be written next
+  const uint32_t nb = (uint32_t)A.n_sweeps * 2u * (uint32_t)L;   // at most 2^20 sweeps per launch
+  uint32_t t = (uint32_t)A.t0, cz = 0;
+  auto advance = [&]() __attribute__((always_inline)) {
+    if (++cz == 2u * (uint32_t)L) {
+      cz = 0;
+      ++t;
+    }
+  };
+  auto fill = [&](uint32_t slot) __attribute__((always_inline)) {
     for (int g = 0; g < NG; ++g) {
       const u32x4 w = philox4x32_10_u((cz << 8) | (uint32_t)g, t, real_id, ctr3, key0, key1);
       lds_store_u32x4(rbase + slot * ws_slot_bytes<L>() + (uint32_t)(g * 64 + lane) * 16u, w);
     }
   };
-  fill(0, 0u);
-  fill(1, 1u);
+  if (nb > 0u) fill(0u);
+  advance();
+  if (nb > 1u) fill(1u);
+  advance();
   __syncthreads();   // tables staged, blocks 0 and 1 written
   uint32_t slot = 2;
-  for (int64_t b = 0; b < nb; ++b) {
-    fill(b + 2, slot);
+  for (uint32_t b = 0; b < nb; ++b) {
+    if (b + 2u < nb) fill(slot);   // block b + 2
+    advance();
     slot = slot == 2u ? 0u : slot + 1u;
     __syncthreads();   // the sampling wave has finished block b
   }
