@@ -236,6 +236,7 @@ def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0
     b = make_batch([L] * n_real, first_real_id=first_id)
     b.wl_init(wl_ln_f0)
     done_at = np.full(n_real, -1, np.int64)
+    t_log = time.time()
     for step in range(1, wl_max_steps + 1):
         b.run_sweeps(wl_sweeps)
         info = b.wl_update(wl_flat, wl_final)
@@ -243,6 +244,10 @@ def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0
         done_at[newly] = step
         if (done_at > 0).all():
             break
+        if log and time.time() - t_log > 60:
+            t_log = time.time()
+            log(f"wang-landau step {step}: {int((done_at > 0).sum())}/{n_real} done, "
+                f"median stage {float(np.median(info['stage'])):.0f}")
     b.wl_to_rec()
     after = iterate(b, sweeps, f_tol, n_max, initialized=True)
     b.close()
