@@ -305,7 +305,7 @@ nfm_status nfm_set_tuning(nfm_ctx* ctx, const nfm_tuning* tuning);
 nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
 
 /* Autotuner for mixed batches (no passage of the paper: a launch-configuration search). Times
- * every candidate tuning (speculation off/on x sweeps per launch {64, 256, 1024} x {per-size
+ * every candidate tuning (speculation off/on x sweeps per launch {16, 64, 256, 1024} x {per-size
  * launches without and (no speculation) with the generator wave, persistent queue with as many
  * workgroups as fit, 4 or 8 per CU}) for calib_sweeps
  * sweeps on the batch itself, then restores spins, walker state and histograms, so the

@@ -1097,7 +1097,7 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     NFM_HIP(c, hipMemcpyAsync(c->ws + l.snap_u64, c->ws + l.ws_u64, 24 * (size_t)l.total_walkers, hipMemcpyDeviceToDevice, c->stream));
     NFM_HIP(c, hipMemcpyAsync(c->ws + l.snap_hist, c->ws + l.hist, 8 * (size_t)l.levels_total, hipMemcpyDeviceToDevice, c->stream));
     std::vector<nfm_tuning> cand;
-    const int chunks[] = {64, 256, 1024};
+    const int chunks[] = {16, 64, 256, 1024};
     for (int spec = 0; spec <= 1; ++spec)
       for (int ch : chunks) {
         // per-size launches: with and without the generator wave (speculation has none)
