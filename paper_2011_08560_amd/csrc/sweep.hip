@@ -12,6 +12,11 @@
 // block is fixed; it is computed for the whole block at once with word-parallel
 // bit operations (six flag strings and a bit-sliced adder). The attempts then run
 // one after the other, since each acceptance reads the walker's current energy.
+//
+// Kernel forms: k_sweeps (one wave per workgroup; compact or expanded table, speculative or
+// plain, tempering), k_sweeps_ws (the sampling wave plus a generator wave that supplies its
+// random words through LDS) and k_sweeps_queue (persistent, over a batch of mixed sizes). All
+// forms draw the same words for the same attempts, so their results are identical.
 #include <algorithm>
 #include <cstdio>
 #include <type_traits>
