@@ -117,6 +117,27 @@ struct PhiloxRun {
   uint32_t c0, c1, c2, c3;
 };
 
+// Rounds R0..R1-1 (R1 <= 3) of a counter whose words 0..2 are uniform across the wave at round
+// 0: the uniform products and xors stay on the scalar unit (uniform round keys), as in
+// philox4x32_10_u.
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds_u(PhiloxRun& s, uint32_t key0, uint32_t key1) {
+  static_assert(R1 <= 3, "from round 3 on two varying words meet");
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = R0; round < R1; ++round) {
+    const uint64_t p0 = (uint64_t)M0 * s.c0;
+    const uint64_t p1 = (uint64_t)M1 * s.c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ s.c1 ^ (key0 + (uint32_t)round * W0);
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ s.c3 ^ (key1 + (uint32_t)round * W1);
+    s.c1 = (uint32_t)p1;
+    s.c3 = (uint32_t)p0;
+    s.c0 = n0;
+    s.c2 = n2;
+  }
+}
+
 template <int R0, int R1>
 __device__ __forceinline__ void philox_rounds(PhiloxRun& s, const PhiloxKeysV& kv) {
   constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;

@@ -283,7 +283,7 @@ __device__ __forceinline__ int clamp_row(int B, int Bmax) {
 // XT (multicanonical, no speculation): the table is expanded on chip to one row per level of
 // the realization (rows outside the stored range repeat its edge rows, as the clamp would), so
 // the row of a level is the level itself and the decision needs no clamp.
-template <int L, bool SPEC, bool PT, bool XT = false, bool WS = false>
+template <int L, bool SPEC, bool PT, bool XT = false, bool WS = false, bool SU = false>
 __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   using G = Geo<L>;
   using PW = typename G::PW;
@@ -574,7 +574,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
             if constexpr (SPEC && !PT) {
               const uint32_t rc = rnd.v[i];
               if constexpr (!WS) {
-                if (i == 0) philox_rounds<0, 3>(pr, kv);
+                if (i == 0) {
+                  if constexpr (SU) philox_rounds_u<0, 3>(pr, key0, key1);
+                  else philox_rounds<0, 3>(pr, kv);
+                }
                 if (i == 1) philox_rounds<3, 5>(pr, kv);
                 if (i == 2) philox_rounds<5, 8>(pr, kv);
                 if (i == 3) philox_rounds<8, 10>(pr, kv);
@@ -612,8 +615,16 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
               //     the round's products do not read: a VALU read of a register an asm statement
               //     wrote costs a wait state, and uniform words stay scalar.
               if constexpr (!WS) {
-                asm volatile("" : "+v"(pr.c1), "+v"(pr.c3));
-                if (i == 0) philox_rounds<0, 3>(pr, kv);
+                // SU: rounds 0-2 act on a counter whose words 0..2 are still uniform, so their
+                // uniform parts go to the scalar unit (pays where several waves share a SIMD and
+                // scalar registers are not short)
+                if constexpr (SU) {
+                  if (i == 0) philox_rounds_u<0, 3>(pr, key0, key1);
+                  if (i > 0) asm volatile("" : "+v"(pr.c1), "+v"(pr.c3));
+                } else {
+                  asm volatile("" : "+v"(pr.c1), "+v"(pr.c3));
+                  if (i == 0) philox_rounds<0, 3>(pr, kv);
+                }
                 if (i == 1) philox_rounds<3, 5>(pr, kv);
                 if (i == 2) philox_rounds<5, 8>(pr, kv);
                 if (i == 3) philox_rounds<8, 10>(pr, kv);
@@ -845,7 +856,9 @@ template <int L, bool SPEC, bool PT, bool XT>
 __global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
   extern __shared__ uint32_t stab[];  // addressed from LDS address 0 by sweep_wave
   (void)stab;
-  sweep_wave<L, SPEC, PT, XT>(A, (int)blockIdx.x);
+  // scalar uniform rounds for the compact and tempering forms (usually several waves per SIMD),
+  // except the L = 6 tempering form, where they cost a resident wave (139 against 125 VGPRs)
+  sweep_wave<L, SPEC, PT, XT, false, !XT && !(PT && L == 6)>(A, (int)blockIdx.x);
 }
 
 // Persistent multicanonical launch over a batch of mixed lattice sizes: each workgroup takes
