@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(lib):
 def test_workspace_validation(lib):
     assert lib.workspace_bytes([8], [64]) > 0
     assert lib.workspace_bytes([4, 12, 6], [64, 128, 64], trace_capacity=10) > lib.workspace_bytes([4, 12, 6], [64, 128, 64])
-    for Ls, Ws in (([3], [64]), ([14], [64]), ([8], [32]), ([8], [0]), ([0], [64])):
+    for Ls, Ws in (([3], [64]), ([14], [64]), ([8], [32]), ([8], [0]), ([0], [64]), ([], []), ([4, 6], [64])):
         with pytest.raises(lib.NfmError) as e:
             lib.workspace_bytes(Ls, Ws)
         assert e.value.status == lib.NFM_EINVAL

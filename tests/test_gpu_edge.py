@@ -1,0 +1,142 @@
+"""Edge cases of the sampler through the C ABI.
+
+The degenerate tables of Eq. (2): every move accepted (the infinite-temperature limit: a sweep
+flips every spin once in turn, so it maps S to -S and, the energy being even in S, ends at the
+energy it began with) and every ratio below 2^-32 (stored as 0: a move is taken only when its
+random word is 0). Both against the oracle on small batches, the first also as a property over a
+full-size batch (L = 6 x 1024 realizations x 64 walkers) in every kernel form; a run of zero
+sweeps; the smallest and the largest lattice side by side with ragged walker counts.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+DSEED, WSEED = 20110856, 0x0DDBA11
+
+ALWAYS = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def nfm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_08560_amd import nfm as m
+    m.lib()
+    return m
+
+
+def _batch(nfm, Ls, Ws, first=0):
+    b = nfm.Batch(Ls, Ws, DSEED, WSEED, first_real_id=first)
+    b.init_couplings()
+    b.init_spins()
+    b.compute_energies()
+    return b
+
+
+def _uniform_tables(b, value):
+    for r in range(b.n_real):
+        K = b.levels(r)
+        b.set_thresholds(r, np.full((K, 8), value, np.uint32), 0)
+        b.set_rt_bounds(r, b.e_base(r), 0)
+
+
+@pytest.mark.parametrize("spec,ws", [(0, 0), (0, 1), (1, 1), (1, 2)])
+def test_always_accept_full_size(nfm, spec, ws):
+    """Every attempt accepted: after an odd number of sweeps every walker holds -S0 at E0, after
+    an even number S0; each sweep ends at E0, so the histogram holds all counts at E0's level."""
+    L, R, W = 6, 1024, 64
+    print("always accept: L", L, "realizations", R, "speculate", spec, "ws", ws, flush=True)
+    b = _batch(nfm, [L] * R, [W] * R)
+    S0 = b.get_spins(0, b.n_walkers).reshape(R * W, L ** 3)
+    E0 = b.read_walkers()["E"].copy()
+    _uniform_tables(b, ALWAYS)
+    b.set_tuning(speculate=spec, sweeps_per_launch=2, ws=ws)
+    for n, sign in ((3, -1), (1, 1)):
+        b.run_sweeps(n)
+        S = b.get_spins(0, b.n_walkers).reshape(R * W, L ** 3)
+        assert np.array_equal(S, sign * S0)
+        assert np.array_equal(b.read_walkers()["E"], E0)
+    H = b.read_histograms()
+    for r in range(R):
+        off = b.level_offset(r)
+        k = (E0[r * W:(r + 1) * W] - b.e_base(r)) // 4
+        want = np.bincount(k, minlength=b.levels(r)).astype(np.uint64) * 4
+        assert np.array_equal(H[off:off + b.levels(r)], want), r
+    b.close()
+
+
+@pytest.mark.parametrize("value", [0, ALWAYS])
+@pytest.mark.parametrize("L", [2, 4, 6])
+def test_uniform_tables_match_oracle(nfm, orc, L, value):
+    """The two degenerate tables on a small batch against the oracle, bit for bit (walker
+    records include the minima of the energies visited inside the sweeps)."""
+    R, W, T = 2, 64, 24
+    b = _batch(nfm, [L] * R, [W] * R, first=5)
+    _uniform_tables(b, value)
+    b.run_sweeps(T)
+    ws = b.read_walkers()
+    H = b.read_histograms()
+    spins = b.get_spins(0, b.n_walkers).reshape(R * W, L ** 3)
+    for r in range(R):
+        J = orc.couplings(L, DSEED, 5 + r)
+        K, eb = orc.n_levels(L, J), orc.e_base(L, J)
+        thr = np.full((K, 8), value, np.uint32)
+        Href = np.zeros(K, np.uint64)
+        for w in range(W):
+            s = orc.spins(L, WSEED, 5 + r, w)
+            wr = orc.new_walkers(1, orc.energy(L, J, s))
+            orc.muca_sweeps(L, J, s, wr, thr, 0, eb, 0, WSEED, 5 + r, w, 0, T, hist=Href)
+            g = r * W + w
+            assert np.array_equal(spins[g], s), (r, w)
+            for f in ("E", "E_min", "rt_state", "new_min", "rt_count", "t_first", "t_last"):
+                assert ws[f][g] == wr[f][0], (f, r, w)
+        off = b.level_offset(r)
+        assert np.array_equal(H[off:off + K], Href), r
+    b.close()
+
+
+def test_zero_sweeps_changes_nothing(nfm):
+    b = _batch(nfm, [4, 6], [64, 128])
+    b.rec_init(1, 1.0, -1.0)
+    b.run_sweeps(5)
+    before = (b.get_spins(0, b.n_walkers), b.read_walkers(), b.read_histograms(), b.sweep_counter)
+    b.run_sweeps(0)
+    after = (b.get_spins(0, b.n_walkers), b.read_walkers(), b.read_histograms(), b.sweep_counter)
+    for x, y in zip(before, after):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    b.close()
+
+
+def test_smallest_and_largest_lattice_ragged(nfm, orc):
+    """L = 2 (every site its own neighbour's neighbour across both faces) beside L = 12, the
+    largest the kernels take, with walker counts 192 / 64 / 128."""
+    Ls, Ws, T = [2, 12, 2], [192, 64, 128], 6
+    b = _batch(nfm, Ls, Ws, first=300)
+    refs = []
+    for r, L in enumerate(Ls):
+        J = orc.couplings(L, DSEED, 300 + r)
+        K, eb = orc.n_levels(L, J), orc.e_base(L, J)
+        lnw = -0.4 * (eb + 4 * np.arange(K, dtype=np.float64))
+        k_top = (-eb + 3) // 4
+        thr, row0 = orc.build_thresholds(K, lnw[:k_top + 1], 0, k_top)
+        b.set_thresholds(r, thr, row0)
+        b.set_rt_bounds(r, eb, 0)
+        refs.append((L, J, K, eb, thr, row0))
+    b.run_sweeps(T)
+    ws = b.read_walkers()
+    H = b.read_histograms()
+    for r, (L, J, K, eb, thr, row0) in enumerate(refs):
+        w0 = b.walker_offset(r)
+        spins = b.get_spins(w0, Ws[r]).reshape(Ws[r], L ** 3)
+        Href = np.zeros(K, np.uint64)
+        for w in range(Ws[r]):
+            s = orc.spins(L, WSEED, 300 + r, w)
+            wr = orc.new_walkers(1, orc.energy(L, J, s))
+            orc.muca_sweeps(L, J, s, wr, thr, row0, eb, 0, WSEED, 300 + r, w, 0, T, hist=Href)
+            assert np.array_equal(spins[w], s), (r, w)
+            for f in ("E", "E_min", "rt_count"):
+                assert ws[f][w0 + w] == wr[f][0], (f, r, w)
+        assert np.array_equal(H[b.level_offset(r):b.level_offset(r) + K], Href), r
+    b.close()
