@@ -175,7 +175,10 @@ nfm_status nfm_set_rt_bounds(nfm_ctx* ctx, int32_t r, int32_t e_bot, int32_t e_t
  * walker's minimum and round-trip state are updated (stamp t*N + a + 1); after
  * every sweep its level is added to its realization's histogram and its energy
  * to its trace (while fewer than trace_capacity sweeps have been traced since
- * the last nfm_reset_trace). Sec. II, Eq. (2); Sec. III. */
+ * the last nfm_reset_trace). Sec. II, Eq. (2); Sec. III. n_sweeps = 0 changes no state.
+ * NFM_ESTATE before couplings and every realization's table are set; NFM_ERANGE when the
+ * context's sweep counter would pass 2^32 - 1 (the sweep index is one word of the random
+ * stream's counter). */
 nfm_status nfm_run_sweeps(nfm_ctx* ctx, uint64_t n_sweeps);
 
 /* Histograms: nfm_levels_total() uint64; realization r's count of level k is at
