@@ -112,7 +112,10 @@ nfm_status nfm_workspace_bytes(const nfm_batch_desc* desc, size_t* bytes);
  * by the library. */
 nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_workspace,
                       size_t workspace_bytes, int device, void* hip_stream);
+/* Waits for the context's stream, then frees the context's host-side state (NULL is a no-op);
+ * the device workspace stays the caller's. */
 void nfm_destroy(nfm_ctx* ctx);
+/* Message of the context's last failed call; owned by the context, valid until its next call. */
 const char* nfm_last_error(const nfm_ctx* ctx);
 
 /* Geometry queries (host-side, no synchronization). */
@@ -324,6 +327,8 @@ typedef struct {
 nfm_status nfm_autotune(nfm_ctx* ctx, int32_t calib_sweeps, const char* cache_path, nfm_tune_result* results,
                         int32_t max_results, int32_t* n_results, nfm_tuning* best);
 
+/* Waits for every launch on the context's stream; NFM_EDEVICE reports a device error raised by
+ * an earlier asynchronous call. */
 nfm_status nfm_sync(nfm_ctx* ctx);
 /* Name of the sweep kernel form the last sweep launch on the calling host thread used, e.g.
  * "k_sweeps_ws<6>" (a report for benchmarks; "none" before any launch). */
@@ -458,6 +463,7 @@ double nfm_upper_gamma(double a, double x);
 nfm_status nfm_frechet_fit(const double* tau, int64_t n, int32_t method, nfm_frechet* fit, double* objective);
 nfm_status nfm_relative_performance(const double* tau_m, const double* tau_ref, int64_t n, double eps,
                                     int32_t method, int32_t blocks, nfm_ratio* out);
+/* Message of the calling thread's last failed statistics call (thread-local storage). */
 const char* nfm_stats_last_error(void);
 
 /* ---------------------------------------------------------------------------------------
@@ -512,6 +518,8 @@ int32_t nfm_mlp_n_params(void);
 nfm_status nfm_mlp_workspace_bytes(int32_t batch_max, size_t* bytes);
 nfm_status nfm_mlp_create(nfm_mlp** out, int32_t batch_max, void* dev_workspace, size_t workspace_bytes,
                           int device, void* hip_stream);
+/* Waits for the network's stream, then frees its host-side state (NULL is a no-op); the device
+ * workspace stays the caller's. last_error: message of its last failed call, owned by it. */
 void nfm_mlp_destroy(nfm_mlp* mlp);
 const char* nfm_mlp_last_error(const nfm_mlp* mlp);
 /* Glorot-uniform weights from the Philox stream (counter (q >> 2, layer, 0, 6), key = seed),
@@ -526,10 +534,13 @@ nfm_status nfm_mlp_forward(nfm_mlp* mlp, const float* dev_x, int32_t B, float* d
 /* Loss and gradient (kept for nfm_mlp_adam); host_loss (optional) synchronizes. */
 nfm_status nfm_mlp_loss_grad(nfm_mlp* mlp, const float* dev_x, const float* dev_t, const float* dev_mask,
                              int32_t B, float* host_loss);
+/* One Adam step (step count t + 1, bias corrections 1 - beta^t) from the gradient the last
+ * nfm_mlp_loss_grad left; asynchronous. NFM_EINVAL unless lr > 0, 0 <= beta1, beta2 < 1, eps > 0. */
 nfm_status nfm_mlp_adam(nfm_mlp* mlp, float lr, float beta1, float beta2, float eps);
 /* loss_grad + adam(lr, 0.9, 0.999, 1e-8), asynchronous. */
 nfm_status nfm_mlp_train_step(nfm_mlp* mlp, const float* dev_x, const float* dev_t, const float* dev_mask,
                               int32_t B, float lr);
+/* Loss of the last nfm_mlp_loss_grad or nfm_mlp_train_step on the stream; synchronizes. */
 nfm_status nfm_mlp_last_loss(nfm_mlp* mlp, float* host_loss);
 /* BF16 copy of the current weights, then inference with it. */
 nfm_status nfm_mlp_to_bf16(nfm_mlp* mlp);
