@@ -67,13 +67,24 @@ static hipError_t gemm(int M, int N, int K, const float* A, int lda, const float
   return hipGetLastError();
 }
 
-// Column sums of X [M x N] (bias gradients), one thread per column, rows in order.
-__global__ void k_colsum(int M, int N, const float* __restrict__ X, float* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// Column sums of X [M x N] (bias gradients; N a multiple of 16). A block of 256 threads takes 16
+// columns: thread (slice, col) sums rows slice, slice + 16, ... in order, then the 16 slices of a
+// column are added in order, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_colsum(int M, int N, const float* __restrict__ X, float* __restrict__ out) {
+  __shared__ float part[16][17];
+  const int col = threadIdx.x & 15, slice = threadIdx.x >> 4;
+  const int j = blockIdx.x * 16 + col;
   float s = 0.f;
-  for (int i = 0; i < M; ++i) s += X[(size_t)i * N + j];
-  out[j] = s;
+  if (j < N)
+    for (int i = slice; i < M; i += 16) s += X[(size_t)i * N + j];
+  part[slice][col] = s;
+  __syncthreads();
+  if (slice == 0 && j < N) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += part[k][col];
+    out[j] = t;
+  }
 }
 
 // Xn [Bp x 96] = (X - mean) / sd on the 81 inputs of the first B rows, zero elsewhere.
@@ -88,14 +99,16 @@ __global__ void k_normalize(int B, int Bp, const float* __restrict__ X, const fl
 }
 
 // Masked mean squared error L = sum m (y - t)^2 / sum m over the first B rows, and its gradient
-// dY = 2 m (y - t) / sum m (zero on padded rows). One block; sums in a fixed tree order.
-__global__ void __launch_bounds__(256) k_loss(int B, int Bp, const float* __restrict__ Y, const float* __restrict__ T,
-                                              const float* __restrict__ Mk, float* __restrict__ dY,
-                                              float* __restrict__ loss) {
+// dY = 2 m (y - t) / sum m (zero on padded rows), in two passes with sums in a fixed order.
+// Pass 1: block b sums m and m (y - t)^2 over its contiguous share of the n = B * 256 elements
+// (per thread in order, then a tree over the block) into part[b] and part[kMlpLossBlocks + b].
+__global__ void __launch_bounds__(256) k_loss_partial(int n, const float* __restrict__ Y, const float* __restrict__ T,
+                                                      const float* __restrict__ Mk, float* __restrict__ part) {
   __shared__ float s_m[256], s_e[256];
+  const int chunk = (n + kMlpLossBlocks - 1) / kMlpLossBlocks;
+  const int e0 = blockIdx.x * chunk, e1 = min(n, e0 + chunk);
   float sm = 0.f, se = 0.f;
-  const int n = B * kMlpOut;
-  for (int e = threadIdx.x; e < n; e += 256) {
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
     const float m = Mk[e], d = Y[e] - T[e];
     sm += m;
     se += m * d * d;
@@ -110,11 +123,36 @@ __global__ void __launch_bounds__(256) k_loss(int B, int Bp, const float* __rest
     }
     __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_m[0];
+    part[kMlpLossBlocks + blockIdx.x] = s_e[0];
+  }
+}
+
+// Pass 2: every block adds the partial sums in the same tree order (so all blocks hold the same
+// total), block 0 stores the loss, and each thread writes one element of dY [Bp x 256].
+__global__ void __launch_bounds__(256) k_loss_final(int n, int total, const float* __restrict__ Y,
+                                                    const float* __restrict__ T, const float* __restrict__ Mk,
+                                                    const float* __restrict__ part, float* __restrict__ dY,
+                                                    float* __restrict__ loss) {
+  __shared__ float s_m[kMlpLossBlocks], s_e[kMlpLossBlocks];
+  if ((int)threadIdx.x < kMlpLossBlocks) {
+    s_m[threadIdx.x] = part[threadIdx.x];
+    s_e[threadIdx.x] = part[kMlpLossBlocks + threadIdx.x];
+  }
+  __syncthreads();
+  for (int h = kMlpLossBlocks / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s_m[threadIdx.x] += s_m[threadIdx.x + h];
+      s_e[threadIdx.x] += s_e[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
   const float msum = s_m[0];
   const float inv = msum > 0.f ? 1.0f / msum : 0.f;
-  if (threadIdx.x == 0) loss[0] = s_e[0] * inv;
-  for (int e = threadIdx.x; e < Bp * kMlpOut; e += 256)
-    dY[e] = e < n ? 2.0f * Mk[e] * (Y[e] - T[e]) * inv : 0.f;
+  if (blockIdx.x == 0 && threadIdx.x == 0) loss[0] = s_e[0] * inv;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < total) dY[e] = e < n ? 2.0f * Mk[e] * (Y[e] - T[e]) * inv : 0.f;
 }
 
 // Adam with bias correction: c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
@@ -244,7 +282,11 @@ hipError_t mlp_loss_grad(const MlpBuffers& m, const float* X, const float* T, co
                          hipStream_t s) {
   hipError_t e = mlp_forward_f32(m, X, B, Bp, m.Y, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, B, Bp, m.Y, T, Mk, m.dY, m.loss);
+  static_assert(kMlpLossBlocks <= 256 && (kMlpLossBlocks & (kMlpLossBlocks - 1)) == 0, "loss partials");
+  hipLaunchKernelGGL(k_loss_partial, dim3(kMlpLossBlocks), dim3(256), 0, s, B * kMlpOut, m.Y, T, Mk, m.loss + 1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_loss_final, dim3((Bp * kMlpOut + 255) / 256), dim3(256), 0, s, B * kMlpOut, Bp * kMlpOut, m.Y, T,
+                     Mk, m.loss + 1, m.dY, m.loss);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const float* P = m.params;
   float* G = m.grads;
@@ -253,7 +295,7 @@ hipError_t mlp_loss_grad(const MlpBuffers& m, const float* X, const float* T, co
   if ((e = gemm<true, false, 0>(H, kMlpOut, Bp, m.A3, H, m.dY, kMlpOut, G + mlp_w_off(3), kMlpOut, nullptr, nullptr,
                                 nullptr, s)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_colsum, dim3((kMlpOut + 255) / 256), dim3(256), 0, s, Bp, kMlpOut, m.dY, G + mlp_b_off(3));
+  hipLaunchKernelGGL(k_colsum, dim3(kMlpOut / 16), dim3(256), 0, s, Bp, kMlpOut, m.dY, G + mlp_b_off(3));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // dZ3 = (dY W3^T) * gelu'(Z3)
   if ((e = gemm<false, true, 3>(Bp, H, kMlpOut, m.dY, kMlpOut, P + mlp_w_off(3), kMlpOut, m.dZa, H, nullptr, m.Z3,
@@ -262,7 +304,7 @@ hipError_t mlp_loss_grad(const MlpBuffers& m, const float* X, const float* T, co
   if ((e = gemm<true, false, 0>(H, H, Bp, m.A2, H, m.dZa, H, G + mlp_w_off(2), H, nullptr, nullptr, nullptr, s)) !=
       hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(H), 0, s, Bp, H, m.dZa, G + mlp_b_off(2));
+  hipLaunchKernelGGL(k_colsum, dim3(H / 16), dim3(256), 0, s, Bp, H, m.dZa, G + mlp_b_off(2));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = gemm<false, true, 3>(Bp, H, H, m.dZa, H, P + mlp_w_off(2), H, m.dZb, H, nullptr, m.Z2, nullptr, s)) !=
       hipSuccess)
@@ -270,7 +312,7 @@ hipError_t mlp_loss_grad(const MlpBuffers& m, const float* X, const float* T, co
   if ((e = gemm<true, false, 0>(H, H, Bp, m.A1, H, m.dZb, H, G + mlp_w_off(1), H, nullptr, nullptr, nullptr, s)) !=
       hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(H), 0, s, Bp, H, m.dZb, G + mlp_b_off(1));
+  hipLaunchKernelGGL(k_colsum, dim3(H / 16), dim3(256), 0, s, Bp, H, m.dZb, G + mlp_b_off(1));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = gemm<false, true, 3>(Bp, H, H, m.dZb, H, P + mlp_w_off(1), H, m.dZa, H, nullptr, m.Z1, nullptr, s)) !=
       hipSuccess)
@@ -278,7 +320,7 @@ hipError_t mlp_loss_grad(const MlpBuffers& m, const float* X, const float* T, co
   if ((e = gemm<true, false, 0>(kMlpInPad, H, Bp, m.Xn, kMlpInPad, m.dZa, H, G + mlp_w_off(0), H, nullptr, nullptr,
                                 nullptr, s)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(H), 0, s, Bp, H, m.dZa, G + mlp_b_off(0));
+  hipLaunchKernelGGL(k_colsum, dim3(H / 16), dim3(256), 0, s, Bp, H, m.dZa, G + mlp_b_off(0));
   return hipGetLastError();
 }
 

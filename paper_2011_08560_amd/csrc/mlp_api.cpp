@@ -44,7 +44,7 @@ MlpLayout mlp_layout(int batch_max) {
   l.Xb = take(2 * Bp * nfm::kMlpInPad);
   l.Hb1 = take(2 * Bp * H);
   l.Hb2 = take(2 * Bp * H);
-  l.loss = take(4);
+  l.loss = take(4 * (1 + 2 * nfm::kMlpLossBlocks));   // the loss, then the partial sums of its reduction
   l.total = off;
   return l;
 }

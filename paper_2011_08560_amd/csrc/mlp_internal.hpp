@@ -12,6 +12,8 @@
 namespace nfm {
 
 constexpr int kMlpIn = 81, kMlpInPad = 96, kMlpHid = 128, kMlpOut = 256;
+// Blocks of the loss's first reduction pass; their partial sums follow the loss in its buffer.
+constexpr int kMlpLossBlocks = 64;
 
 __host__ __device__ constexpr int mlp_in(int layer) { return layer == 0 ? kMlpInPad : kMlpHid; }
 __host__ __device__ constexpr int mlp_out(int layer) { return layer == 3 ? kMlpOut : kMlpHid; }

@@ -13,7 +13,8 @@ only holds device tensors and shuffles minibatches.
 
 trains on realizations of the listed sizes (ids from 0), evaluates on fresh realizations (ids
 from 10^6) with and without the seed under the same seeds, sweeps per round and flatness
-tolerance, and prints one JSON line with the iterations to converge of both arms.
+tolerance, and prints one JSON line with the iterations to converge of both arms. With
+--bench-net it only times the network's training steps and BF16 inference.
 """
 from __future__ import annotations
 
@@ -188,6 +189,44 @@ def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID, log
     return it_plain, it_seed, k_seed
 
 
+def bench_net(batch=256, steps=200, n_infer=16384, seed=7):
+    """Throughput of the network's kernels on synthetic inputs (standard normal x, targets of
+    spread 0.1, full masks): FP32 training steps (forward, back-propagation, Adam) on one
+    minibatch of `batch` rows, and BF16 inference over n_infer rows in chunks of `batch`. A
+    forward pass costs 2 x 75904 flops per row (81-128-128-128-256), a training step about three
+    times that."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    x = torch.randn(batch, nfm.Mlp.N_IN, generator=g).cuda()
+    y = (0.1 * torch.randn(batch, nfm.Mlp.N_OUT, generator=g)).cuda()
+    m = torch.ones(batch, nfm.Mlp.N_OUT).cuda()
+    mlp = nfm.Mlp(batch_max=batch)
+    mlp.init(seed)
+    for _ in range(10):
+        mlp.train_step(x, y, m, lr=1e-3)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        mlp.train_step(x, y, m, lr=1e-3)
+    torch.cuda.synchronize()
+    dt_train = (time.perf_counter() - t) / steps
+    xi = torch.randn(n_infer, nfm.Mlp.N_IN, generator=g).cuda()
+    mlp.to_bf16()
+    infer(mlp, xi)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        infer(mlp, xi)
+    torch.cuda.synchronize()
+    dt_inf = (time.perf_counter() - t) / reps
+    fwd = 2 * 75904
+    return {"batch": batch, "train_step_us": dt_train * 1e6, "train_rows_per_s": batch / dt_train,
+            "train_tflops": 3 * fwd * batch / dt_train / 1e12, "infer_rows": n_infer,
+            "infer_us": dt_inf * 1e6, "infer_rows_per_s": n_infer / dt_inf,
+            "infer_tflops": fwd * n_infer / dt_inf / 1e12, "final_loss": mlp.last_loss()}
+
+
 def summary(it_plain, it_seed, k_seed, n_max):
     def arm(it):
         c = it > n_max
@@ -209,7 +248,12 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--bench-net", action="store_true",
+                    help="only time the network's training steps and BF16 inference on synthetic inputs")
     args = ap.parse_args(argv)
+    if args.bench_net:
+        print(json.dumps(bench_net(seed=args.seed)))
+        return
     t0 = time.time()
     log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
     per_L = int(math.ceil(args.train_real / len(args.train_L)))
