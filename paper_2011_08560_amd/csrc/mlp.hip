@@ -25,21 +25,32 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 //   EPI 0: C = acc              EPI 1: C = acc + bias[col]
 //   EPI 2: C2 = acc + bias[col] (pre-activation), C = gelu(C2)
 //   EPI 3: C = acc * gelu'(aux[row][col])
-template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(64) k_gemm_f32(int M, int N, int K, const float* __restrict__ A, int lda,
-                                                 const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
-                                                 const float* __restrict__ bias, const float* __restrict__ aux,
-                                                 float* __restrict__ C2) {
+// One workgroup per 16 x 16 tile of C; its S waves each reduce a contiguous K / S share, and wave 0
+// adds the other waves' partial tiles in wave order before the epilogue (a fixed order).
+template <bool TA, bool TB, int EPI, int S>
+__global__ void __launch_bounds__(64 * S) k_gemm_f32(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                     const float* __restrict__ B, int ldb, float* __restrict__ C,
+                                                     int ldc, const float* __restrict__ bias,
+                                                     const float* __restrict__ aux, float* __restrict__ C2) {
+  __shared__ v4f part[S > 1 ? S - 1 : 1][64];
   const int tj = blockIdx.x, ti = blockIdx.y;
-  const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, li = l & 15, lk = l >> 4;
   const int ia = ti * 16 + li, jb = tj * 16 + li;
+  const int kper = K / S, kb = wv * kper;
   v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 8
-  for (int k0 = 0; k0 < K; k0 += 4) {
+  for (int k0 = kb; k0 < kb + kper; k0 += 4) {
     const int k = k0 + lk;
     const float a = TA ? A[(size_t)k * lda + ia] : A[(size_t)ia * lda + k];
     const float b = TB ? B[(size_t)jb * ldb + k] : B[(size_t)k * ldb + jb];
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  if constexpr (S > 1) {
+    if (wv > 0) part[wv - 1][l] = acc;
+    __syncthreads();
+    if (wv > 0) return;
+#pragma unroll
+    for (int q = 0; q < S - 1; ++q) acc += part[q][l];
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -62,8 +73,13 @@ template <bool TA, bool TB, int EPI>
 static hipError_t gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
                        const float* bias, const float* aux, float* C2, hipStream_t s) {
   if (M % 16 || N % 16 || K % 4 || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm_f32<TA, TB, EPI>), dim3(N / 16, M / 16), dim3(64), 0, s, M, N, K, A, lda, B, ldb, C, ldc,
-                     bias, aux, C2);
+  // the layers' K (96, 128, 256) split over four waves; any other multiple of 4 runs on one
+  if (K % 16 == 0)
+    hipLaunchKernelGGL((k_gemm_f32<TA, TB, EPI, 4>), dim3(N / 16, M / 16), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                       ldc, bias, aux, C2);
+  else
+    hipLaunchKernelGGL((k_gemm_f32<TA, TB, EPI, 1>), dim3(N / 16, M / 16), dim3(64), 0, s, M, N, K, A, lda, B, ldb, C,
+                       ldc, bias, aux, C2);
   return hipGetLastError();
 }
 
