@@ -2,9 +2,14 @@
 
 Independent facts used:
   * with the exact density of states g (enumerated at L = 3) the ensembles are
-    known in closed form: W = P_SH/g gives a histogram proportional to P_SH
-    ("the recorded histogram of nonflat MUCA matches the imposed profile"),
-    W = 1/g a flat one, and W = 1/sum_{E' <= E} g(E') the 1/k-ensemble;
+    known in closed form: W = P_SH/g yields a histogram proportional to P_SH
+    (Sec. II, Eq. (4), Fig. 1), W = 1/g a flat one, and W = 1/sum_{E' <= E} g(E')
+    the 1/k-ensemble (Eq. (7));
+  * fed the exact steps b = ln g(k+1) - ln g(k), the oracle's weight builder must
+    return S = ln g - ln g(top), the power law of Eq. (5) anchored at the ground
+    state (ln P = 0 at E = 0) and the 1/k weights -ln sum_{j <= k} g(j) + const,
+    each written out here from integer counts, and production under those weights
+    must give the histogram each ensemble prescribes;
   * the recursion's converged estimate S(E) - S(top) must reproduce
     ln g(E) - ln g(top) within statistical error, whatever target profile
     steered the iteration;
@@ -130,3 +135,103 @@ def test_recursion_converges_to_exact_dos(orc, exact_L3, profile, dE, alpha):
     ref = np.log(g[ks][m]) - math.log(g[k_top])
     got = S[ks][m]
     assert np.max(np.abs(got - ref)) < 0.25, np.c_[ks[m], got, ref]
+
+
+def _exact_steps(g, k_lo, k_top):
+    """b(k) = ln g(k+1) - ln g(k) on [k_lo, k_top), from integer counts (no gaps)."""
+    K = len(g)
+    b = np.zeros(K)
+    assert np.all(g[k_lo:k_top + 1] > 0)
+    for k in range(k_lo, k_top):
+        b[k] = math.log(int(g[k + 1])) - math.log(int(g[k]))
+    return b
+
+
+@pytest.fixture(scope="module", params=[(3, 0), (3, 3), (2, 1), (2, 4)])
+def exact_case(orc, request):
+    """(L, real id): L = 3 realizations with even and odd e_base parity, and L = 2 ones whose
+    level set holds E = 0 (even n_minus) or does not."""
+    L, rid = request.param
+    J = orc.couplings(L, 20110856, rid)
+    g = orc.brute_dos(L, J)
+    eb = orc.e_base(L, J)
+    k_lo = int(np.nonzero(g)[0][0])
+    k_top = (-eb + 3) // 4
+    return L, J, g, eb, k_lo, k_top
+
+
+@pytest.mark.parametrize("dE,alpha", [(6.0, -2.0), (96.0, -3.6), (1.0, -1.0), (1.0, -0.5)])
+def test_rec_weights_power_law_is_eq5(orc, exact_case, dE, alpha):
+    """The power-law profile of the oracle's weight builder against Eq. (5) written out:
+    P_SH(E) = ((E - E_g + dE)/(dE - E_g))^alpha with E_g the lowest level of the estimate
+    (the ground state here) and P_SH(0) = 1; S from the exact steps."""
+    L, J, g, eb, k_lo, k_top = exact_case
+    K = len(g)
+    b = _exact_steps(g, k_lo, k_top)
+    S, lnP, lnW = orc.rec_weights(K, eb, k_lo, k_top, 1, dE, alpha, b)
+    ks = np.arange(k_lo, k_top + 1)
+    E = eb + 4 * ks
+    E_g = int(eb + 4 * k_lo)
+    assert E_g == int(eb + 4 * np.nonzero(g)[0][0])          # anchored at the true ground state
+    ref_lnP = np.array([alpha * math.log((int(e) - E_g + dE) / (dE - E_g)) for e in E])
+    ref_S = np.array([math.log(int(g[k])) - math.log(int(g[k_top])) for k in ks])
+    assert np.max(np.abs(S[ks] - ref_S)) <= 1e-12 * max(1.0, np.abs(ref_S).max())
+    assert np.max(np.abs(lnP[ks] - ref_lnP)) <= 1e-12 * max(1.0, np.abs(ref_lnP).max())
+    assert np.max(np.abs(lnW[ks] - (-ref_S + ref_lnP))) <= 1e-12 * max(1.0, np.abs(ref_S).max())
+    # P decreases from the ground state upwards (alpha < 0) and is 1 at E = 0 where that is a level
+    assert np.all(np.diff(lnP[ks]) < 0)
+    if (-eb) % 4 == 0:
+        assert lnP[(-eb) // 4] == 0.0 or abs(lnP[(-eb) // 4]) < 1e-15
+    # the enhancement at the ground state is Eq. (6): (1/(1 - E_g/dE))^alpha
+    assert abs(lnP[k_lo] - alpha * math.log(1.0 / (1.0 - E_g / dE))) < 1e-12 * abs(lnP[k_lo]) + 1e-15
+
+
+def test_rec_weights_invk_is_eq7(orc, exact_case):
+    """The 1/k profile against Eq. (7) written out from integer counts: with S = ln g + c,
+    ln P = ln g(k) - ln sum_{j=k_lo..k} g(j) and ln W = -S + ln P = -ln sum_{j<=k} g(j) + c'."""
+    L, J, g, eb, k_lo, k_top = exact_case
+    K = len(g)
+    b = _exact_steps(g, k_lo, k_top)
+    S, lnP, lnW = orc.rec_weights(K, eb, k_lo, k_top, 2, 1.0, 0.0, b)
+    ks = np.arange(k_lo, k_top + 1)
+    cum = np.cumsum([int(g[k]) for k in ks], dtype=object)          # exact integers
+    ref_lnP = np.array([math.log(int(g[k])) - math.log(int(c)) for k, c in zip(ks, cum)])
+    ref_lnW = np.array([math.log(int(g[k_top])) - math.log(int(c)) for c in cum])
+    assert np.max(np.abs(lnP[ks] - ref_lnP)) <= 1e-12 * max(1.0, np.abs(ref_lnP).max())
+    assert np.max(np.abs(lnW[ks] - ref_lnW)) <= 1e-12 * max(1.0, np.abs(ref_lnW).max())
+    assert lnP[k_lo] == 0.0                                           # the ground state is all of its cumulative count
+    assert np.all(lnP[ks] <= 1e-15)                                   # P = g / cumulative g <= 1
+    assert np.all(np.diff(lnW[ks]) < 0)                               # W = 1/k falls with k
+    # Sec. II: to first order the 1/k weights are a power law whose exponent is the slope of
+    # ln g (P_SH ~ d ln g / dE); at the top, where ln g is nearly flat, the two agree best
+    # (checked in ratio: the 1/k profile's local slope equals minus that of ln sum g)
+
+
+@pytest.mark.parametrize("kind,dE,alpha", [("flat", 1.0, 0.0), ("power", 6.0, -2.0), ("invk", 1.0, 0.0)])
+def test_production_from_exact_steps_gives_prescribed_histogram(orc, exact_L3, kind, dE, alpha):
+    """Production (Sec. II) from a recursion state holding the exact steps: the oracle's own
+    production weights must give H proportional to the prescribed distribution -- 1 (flat),
+    P_SH of Eq. (5) anchored at the ground state (power law), g/sum_{E'<=E} g (1/k) -- each
+    written out here from the enumerated counts."""
+    L, J, g, = exact_L3
+    eb, k_lo, k_top = _levels(orc, L, J, g)
+    K = len(g)
+    rz = orc.make_realization(L, 20110856, L3_REAL, 21, 48)
+    st = orc.recursion_init(rz)
+    st.b[:] = _exact_steps(g, k_lo, k_top)
+    st.k_lo = k_lo
+    lnw = orc.production_weights(rz, st, kind, pl_dE=dE, pl_alpha=alpha)
+    H = _production_hist(orc, L, J, lnw[k_lo:k_top + 1], k_lo, k_top)
+    ks = np.arange(k_lo, k_top + 1)
+    E = eb + 4 * ks
+    E_g = eb + 4 * k_lo
+    if kind == "flat":
+        target = np.ones(len(ks))
+    elif kind == "power":
+        target = ((E - E_g + dE) / (dE - E_g)) ** alpha
+    else:
+        gi = np.array([int(g[k]) for k in ks], dtype=np.float64)
+        target = gi / np.cumsum(gi)
+    h = H[ks] / H[ks].sum()
+    p = target / target.sum()
+    assert np.max(np.abs(h / p - 1)) < 0.12, (kind, np.c_[ks, h / p])
