@@ -626,7 +626,7 @@ nfm_status nfm_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
   if (!c->couplings) return fail(c, NFM_ESTATE, "run_sweeps: couplings not set");
   for (int r = 0; r < c->n_real; ++r)
     if (c->reals[r].rows < 1) return fail(c, NFM_ESTATE, "run_sweeps: no threshold table, realization " + std::to_string(r));
-  if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
+  if (n_sweeps > (uint64_t)UINT32_MAX - c->sweeps)   // written so that it cannot wrap
     return fail(c, NFM_ERANGE, "run_sweeps: the sweep counter must stay below 2^32");
   nfm_status st = muca_launches(c, c->sweeps, n_sweeps, c->speculate, c->sweeps_per_launch, c->schedule,
                                 c->waves_per_cu, c->hist_mode, c->ws_mode, c->trace_cap);
@@ -807,6 +807,8 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
       h.disorder_seed != c->disorder_seed || h.walker_seed != c->walker_seed || h.trace_cap != c->trace_cap)
     return fail(c, NFM_EINVAL, "restore: checkpoint of a different batch (sizes, walkers, ids, seeds or trace)");
   if (size < ckpt_bytes(c)) return fail(c, NFM_ESIZE, "restore: checkpoint truncated");
+  if (h.sweeps > (uint64_t)UINT32_MAX || h.trace_t0 > h.sweeps || h.pt_t_reset > h.sweeps)
+    return fail(c, NFM_EINVAL, "restore: sweep counters out of range");
   NFM_TRY(c, {
     const char* in = (const char*)host_blob;
     const size_t nT = (size_t)c->n_real * nfm::kMaxReplicas;
@@ -1059,7 +1061,7 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
     if (c->reals[r].rows < 1) return fail(c, NFM_ESTATE, "autotune: no threshold table, realization " + std::to_string(r));
   if (calib_sweeps < 1 || max_results < 0 || (max_results > 0 && !results))
     return fail(c, NFM_EINVAL, "autotune: calib_sweeps >= 1 and a results array of max_results entries");
-  if (c->sweeps + (uint64_t)calib_sweeps > (uint64_t)UINT32_MAX)
+  if ((uint64_t)calib_sweeps > (uint64_t)UINT32_MAX - c->sweeps)
     return fail(c, NFM_ERANGE, "autotune: the sweep counter must stay below 2^32");
   NFM_TRY(c, {
     const std::string key = tune_key(c);
@@ -1338,7 +1340,7 @@ nfm_status nfm_pt_adapt(nfm_ctx* c, double rate_lo, double rate_hi, double* host
 nfm_status nfm_pt_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
   NFM_GUARD(c);
   if (c->pt_M == 0) return fail(c, NFM_ESTATE, "pt_run_sweeps: call nfm_pt_init first");
-  if (c->sweeps + n_sweeps > (uint64_t)UINT32_MAX)
+  if (n_sweeps > (uint64_t)UINT32_MAX - c->sweeps)   // written so that it cannot wrap
     return fail(c, NFM_ERANGE, "pt_run_sweeps: the sweep counter must stay below 2^32");
   uint64_t done = 0;
   while (done < n_sweeps) {

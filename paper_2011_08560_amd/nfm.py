@@ -25,6 +25,31 @@ class NfmError(RuntimeError):
         self.status = status
 
 
+def check_device_tensor(t, device, shape, what: str):
+    """Refuse (ValueError) a tensor the kernels cannot take as a float32 row-major array of
+    exactly `shape` on `device` (a torch.device): every pointer handed to the library must
+    cover what its kernels read and write."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: a torch tensor is required, got {type(t).__name__}")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{what}: dtype float32 required, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(shape)} required, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: a contiguous (row-major) tensor is required")
+    if t.device.type != "cuda" or (device is not None and t.device.index != device.index):
+        raise ValueError(f"{what}: a tensor on {device} is required, got {t.device}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _sweep_count(n) -> int:
+    n = int(n)
+    if n < 0:
+        raise ValueError(f"sweep count must be >= 0, got {n}")
+    return n
+
+
 class BatchDesc(C.Structure):
     _fields_ = [("n_real", C.c_int32), ("L", C.POINTER(C.c_int32)), ("walkers", C.POINTER(C.c_int32)),
                 ("disorder_seed", C.c_uint64), ("walker_seed", C.c_uint64), ("first_real_id", C.c_uint32),
@@ -372,7 +397,7 @@ class Batch:
 
     # sampling and read-back
     def run_sweeps(self, n: int):
-        self._check(self._lib.nfm_run_sweeps(self.ctx, n), "run_sweeps")
+        self._check(self._lib.nfm_run_sweeps(self.ctx, _sweep_count(n)), "run_sweeps")
 
     def read_histograms(self, reset: bool = False) -> np.ndarray:
         out = np.zeros(self.levels_total, np.uint64)
@@ -554,7 +579,7 @@ class Batch:
         return rates, n_out.value
 
     def pt_run_sweeps(self, n: int):
-        self._check(self._lib.nfm_pt_run_sweeps(self.ctx, n), "pt_run_sweeps")
+        self._check(self._lib.nfm_pt_run_sweeps(self.ctx, _sweep_count(n)), "pt_run_sweeps")
 
     def pt_slots(self) -> np.ndarray:
         out = np.zeros(self.n_walkers, np.int32)
@@ -593,7 +618,8 @@ class Batch:
         """Seeded prior from device curves (torch float32 [n_real, 256] on this GPU); returns k_seed
         per realization (-1: rejected, plain start kept)."""
         ks = np.zeros(self.n_real, np.int32)
-        self._check(self._lib.nfm_rec_seed_grid(self.ctx, C.c_void_p(curves.data_ptr()), ks.ctypes.data),
+        pc = check_device_tensor(curves, self.device, (self.n_real, 256), "rec_seed_grid curves")
+        self._check(self._lib.nfm_rec_seed_grid(self.ctx, pc, ks.ctypes.data),
                     "rec_seed_grid")
         return ks
 
@@ -614,7 +640,8 @@ class Batch:
         import torch
         if out is None:
             out = torch.empty((self.n_real, 81), dtype=torch.float32, device=self.device)
-        self._check(self._lib.nfm_features(self.ctx, C.c_void_p(out.data_ptr())), "features")
+        po = check_device_tensor(out, self.device, (self.n_real, 81), "features out")
+        self._check(self._lib.nfm_features(self.ctx, po), "features")
         return out
 
 
@@ -680,30 +707,41 @@ class Mlp:
         self._check(self._lib.nfm_mlp_get_grads(self.ctx, g.ctypes.data), "get_grads")
         return g
 
-    @staticmethod
-    def _p(t):
-        return C.c_void_p(t.data_ptr())
+    def _rows(self, x, what) -> int:
+        B = int(x.shape[0]) if hasattr(x, "shape") and len(x.shape) >= 1 else -1
+        if not 1 <= B <= self.batch_max:
+            raise ValueError(f"{what}: between 1 and {self.batch_max} rows required, got {B}")
+        return B
+
+    def _x(self, x, what):
+        B = self._rows(x, what)
+        return B, check_device_tensor(x, self.device, (B, self.N_IN), what + " x")
+
+    def _y(self, t, B, what):
+        return check_device_tensor(t, self.device, (B, self.N_OUT), what)
 
     def forward(self, x, out=None):
         import torch
-        B = x.shape[0]
+        B, px = self._x(x, "forward")
         if out is None:
             out = torch.empty((B, self.N_OUT), dtype=torch.float32, device=self.device)
-        self._check(self._lib.nfm_mlp_forward(self.ctx, self._p(x), B, self._p(out)), "forward")
+        self._check(self._lib.nfm_mlp_forward(self.ctx, px, B, self._y(out, B, "forward out")), "forward")
         return out
 
     def loss_grad(self, x, t, mask) -> float:
         loss = C.c_float()
-        self._check(self._lib.nfm_mlp_loss_grad(self.ctx, self._p(x), self._p(t), self._p(mask), x.shape[0],
-                                                C.byref(loss)), "loss_grad")
+        B, px = self._x(x, "loss_grad")
+        self._check(self._lib.nfm_mlp_loss_grad(self.ctx, px, self._y(t, B, "loss_grad t"),
+                                                self._y(mask, B, "loss_grad mask"), B, C.byref(loss)), "loss_grad")
         return float(loss.value)
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self._check(self._lib.nfm_mlp_adam(self.ctx, lr, beta1, beta2, eps), "adam")
 
     def train_step(self, x, t, mask, lr=1e-3):
-        self._check(self._lib.nfm_mlp_train_step(self.ctx, self._p(x), self._p(t), self._p(mask), x.shape[0], lr),
-                    "train_step")
+        B, px = self._x(x, "train_step")
+        self._check(self._lib.nfm_mlp_train_step(self.ctx, px, self._y(t, B, "train_step t"),
+                                                 self._y(mask, B, "train_step mask"), B, lr), "train_step")
 
     def last_loss(self) -> float:
         loss = C.c_float()
@@ -715,10 +753,10 @@ class Mlp:
 
     def infer_bf16(self, x, out=None):
         import torch
-        B = x.shape[0]
+        B, px = self._x(x, "infer_bf16")
         if out is None:
             out = torch.empty((B, self.N_OUT), dtype=torch.float32, device=self.device)
-        self._check(self._lib.nfm_mlp_infer_bf16(self.ctx, self._p(x), B, self._p(out)), "infer_bf16")
+        self._check(self._lib.nfm_mlp_infer_bf16(self.ctx, px, B, self._y(out, B, "infer_bf16 out")), "infer_bf16")
         return out
 
 

@@ -3,6 +3,8 @@ symbol declared in include/nfm.h, and validates batch descriptions."""
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -50,3 +52,29 @@ def test_coupling_word_format(lib, orc):
         for d, i in ((0, 0), (1, N - 1), (2, N // 2)):
             JW = (N + 31) // 32
             assert ((int(w[d * JW + i // 32]) >> (i % 32)) & 1) == (1 if J[d * N + i] < 0 else 0)
+
+
+def test_device_tensor_checks_refuse_what_the_kernels_cannot_take(lib):
+    """Every device array the binding hands to the library must be float32, row-major, of the
+    exact shape the kernels assume and on the context's GPU; anything else is refused before
+    the library is called (shown here with CPU and meta tensors: the checks run in that order)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    good_shape = (5, 81)
+    for bad, what in ((torch.zeros(good_shape, dtype=torch.float64), "dtype"),
+                      (torch.zeros((81, 5), dtype=torch.float32).t(), "contiguous"),
+                      (torch.zeros((5, 80), dtype=torch.float32), "shape"),
+                      (torch.zeros((4, 81), dtype=torch.float32), "shape"),
+                      (torch.zeros(5 * 81, dtype=torch.float32), "shape"),
+                      (torch.zeros(good_shape, dtype=torch.float32), "on cuda"),
+                      (torch.zeros(good_shape, dtype=torch.float32, device="meta"), "on cuda"),
+                      (np.zeros(good_shape, np.float32), "torch tensor")):
+        with pytest.raises(ValueError) as e:
+            lib.check_device_tensor(bad, dev, good_shape, "x")
+        assert what.split()[0] in str(e.value) or "tensor" in str(e.value), (what, str(e.value))
+
+
+def test_negative_sweep_counts_are_refused(lib):
+    with pytest.raises(ValueError):
+        lib._sweep_count(-1)
+    assert lib._sweep_count(0) == 0 and lib._sweep_count(2 ** 40) == 2 ** 40

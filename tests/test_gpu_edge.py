@@ -140,3 +140,26 @@ def test_smallest_and_largest_lattice_ragged(nfm, orc):
                 assert ws[f][w0 + w] == wr[f][0], (f, r, w)
         assert np.array_equal(H[b.level_offset(r):b.level_offset(r) + K], Href), r
     b.close()
+
+
+def test_sweep_counts_beyond_the_counter_are_refused(nfm):
+    """A sweep count that would carry the sweep counter past 2^32 - 1 is NFM_ERANGE before any
+    launch, also when the count itself is near 2^64 (no wrap in the check): run_sweeps and
+    pt_run_sweeps through the raw C ABI, and the binding refuses negative counts."""
+    b = _batch(nfm, [4], [64])
+    _uniform_tables(b, ALWAYS)
+    b.run_sweeps(3)
+    lib = nfm.lib()
+    for n in (2 ** 64 - 1, 2 ** 64 - 3, 2 ** 32 - 3, 2 ** 32):
+        assert lib.nfm_run_sweeps(b.ctx, n) == nfm.NFM_ERANGE, n
+    assert b.sweep_counter == 3
+    b.pt_init([0.5, 1.0])
+    for n in (2 ** 64 - 1, 2 ** 32):
+        assert lib.nfm_pt_run_sweeps(b.ctx, n) == nfm.NFM_ERANGE, n
+    with pytest.raises(ValueError):
+        b.run_sweeps(-1)
+    with pytest.raises(ValueError):
+        b.pt_run_sweeps(-1)
+    b.sync()
+    assert b.sweep_counter == 3
+    b.close()
