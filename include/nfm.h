@@ -545,6 +545,15 @@ nfm_status nfm_mlp_last_loss(nfm_mlp* mlp, float* host_loss);
 /* BF16 copy of the current weights, then inference with it. */
 nfm_status nfm_mlp_to_bf16(nfm_mlp* mlp);
 nfm_status nfm_mlp_infer_bf16(nfm_mlp* mlp, const float* dev_x, int32_t B, float* dev_y);
+/* For callers that cannot allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid allocation): the same BF16 inference as nfm_mlp_infer_bf16, same results bit for bit,
+ * with its activations in a static device array of the library (one per GPU, about 1.8 MB, held
+ * until the process ends) instead of the network's workspace. Allocates nothing and calls no
+ * allocating routine; asynchronous on the network's stream. B in [1, 1024] rows (NFM_ERANGE
+ * above, independent of batch_max); dev_x [B x 81] and dev_y [B x 256] floats (device) are the
+ * caller's. Every call on one GPU shares that array: calls that overlap on one GPU (several
+ * streams or threads) race; calls queued on one stream do not. */
+nfm_status nfm_mlp_infer_bf16_noalloc(nfm_mlp* mlp, const float* dev_x, int32_t B, float* dev_y);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -49,6 +50,45 @@ MlpLayout mlp_layout(int batch_max) {
   return l;
 }
 
+// Scratch of the entry point that allocates nothing (nfm_mlp_infer_bf16_noalloc): the BF16
+// activations and the FP32 output rows of one batch of at most kNoAllocRows rows, carved as
+// Xb [rows x 96] bf16, H1 and H2 [rows x 128] bf16, Y [rows x 256] float. Every kernel of the
+// inference writes all of its buffer's rows (padding included) before any is read, so nothing
+// needs clearing between calls. One copy per GPU, held until the process ends; calls that
+// overlap on one GPU share it and race.
+constexpr int kNoAllocRows = 1024;
+constexpr size_t kNoAllocXb = 0;
+constexpr size_t kNoAllocH1 = kNoAllocXb + 2 * (size_t)kNoAllocRows * nfm::kMlpInPad;
+constexpr size_t kNoAllocH2 = kNoAllocH1 + 2 * (size_t)kNoAllocRows * nfm::kMlpHid;
+constexpr size_t kNoAllocY = kNoAllocH2 + 2 * (size_t)kNoAllocRows * nfm::kMlpHid;
+constexpr size_t kNoAllocBytes = kNoAllocY + 4 * (size_t)kNoAllocRows * nfm::kMlpOut;
+static_assert(kNoAllocH1 % 256 == 0 && kNoAllocH2 % 256 == 0 && kNoAllocY % 256 == 0, "aligned regions");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+// In host code this name stands for the array and is not a device address: kernels and copies
+// take the address hipGetSymbolAddress returns for the current device (scratch_address()).
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// The device address of this GPU's copy of the scratch array, looked up once per device with
+// that device current (the caller has made it current). nullptr on failure.
+char* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_dev[device] = (char*)ptr;
+  }
+  return g_scratch_dev[device];
+}
+
 }  // namespace
 
 struct nfm_mlp {
@@ -59,6 +99,7 @@ struct nfm_mlp {
   MlpLayout lay{};
   nfm::MlpBuffers buf{};
   int64_t step = 0;  // Adam steps taken
+  char* scratch = nullptr;  // this device's no-allocation scratch (device address)
   std::string err;
 };
 
@@ -137,6 +178,11 @@ nfm_status nfm_mlp_create(nfm_mlp** out, int32_t batch_max, void* dev_workspace,
   b.loss = (float*)(w + l.loss);
   if (hipSetDevice(device) != hipSuccess || hipMemsetAsync(m->ws, 0, l.total, m->stream) != hipSuccess ||
       hipStreamSynchronize(m->stream) != hipSuccess) {
+    delete m;
+    return NFM_EDEVICE;
+  }
+  m->scratch = scratch_address(device);   // set-up of the no-allocation entry point, once per device
+  if (!m->scratch) {
     delete m;
     return NFM_EDEVICE;
   }
@@ -270,6 +316,24 @@ nfm_status nfm_mlp_infer_bf16(nfm_mlp* m, const float* dev_x, int32_t B, float* 
   if (st != NFM_OK) return st;
   MLP_HIP(m, nfm::mlp_infer_bf16(m->buf, dev_x, B, pad16(B), m->buf.Y, m->stream));
   MLP_HIP(m, hipMemcpyAsync(dev_y, m->buf.Y, 4 * (size_t)B * nfm::kMlpOut, hipMemcpyDeviceToDevice, m->stream));
+  return NFM_OK;
+}
+
+nfm_status nfm_mlp_infer_bf16_noalloc(nfm_mlp* m, const float* dev_x, int32_t B, float* dev_y) {
+  MLP_GUARD(m);
+  if (!dev_x || !dev_y) return mfail(m, NFM_EINVAL, "infer_bf16_noalloc: null device pointer");
+  if (B < 1) return mfail(m, NFM_EINVAL, "infer_bf16_noalloc: at least one row");
+  if (B > kNoAllocRows)
+    return mfail(m, NFM_ERANGE, "infer_bf16_noalloc: at most " + std::to_string(kNoAllocRows) +
+                                    " rows per call (the size of the static scratch), got " + std::to_string(B));
+  if (!m->scratch) return mfail(m, NFM_ESTATE, "infer_bf16_noalloc: no scratch address for this device");
+  nfm::MlpBuffers b = m->buf;   // parameters, normalization and BF16 weights from the network
+  b.Xb = (uint16_t*)(m->scratch + kNoAllocXb);
+  b.Hb1 = (uint16_t*)(m->scratch + kNoAllocH1);
+  b.Hb2 = (uint16_t*)(m->scratch + kNoAllocH2);
+  float* Y = (float*)(m->scratch + kNoAllocY);
+  MLP_HIP(m, nfm::mlp_infer_bf16(b, dev_x, B, pad16(B), Y, m->stream));
+  MLP_HIP(m, hipMemcpyAsync(dev_y, Y, 4 * (size_t)B * nfm::kMlpOut, hipMemcpyDeviceToDevice, m->stream));
   return NFM_OK;
 }
 

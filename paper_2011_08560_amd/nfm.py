@@ -196,6 +196,7 @@ def lib():
         "nfm_mlp_last_loss": (i32, [vp, vp]),
         "nfm_mlp_to_bf16": (i32, [vp]),
         "nfm_mlp_infer_bf16": (i32, [vp, vp, i32, vp]),
+        "nfm_mlp_infer_bf16_noalloc": (i32, [vp, vp, i32, vp]),
     })
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -757,6 +758,17 @@ class Mlp:
         if out is None:
             out = torch.empty((B, self.N_OUT), dtype=torch.float32, device=self.device)
         self._check(self._lib.nfm_mlp_infer_bf16(self.ctx, px, B, self._y(out, B, "infer_bf16 out")), "infer_bf16")
+        return out
+
+    NOALLOC_ROWS = 1024
+
+    def infer_bf16_noalloc(self, x, out):
+        """nfm_mlp_infer_bf16_noalloc: the same inference with the library's static scratch (at most
+        NOALLOC_ROWS rows, any batch_max); the caller passes the output tensor [B, 256]."""
+        B = int(x.shape[0]) if hasattr(x, "shape") and len(x.shape) >= 1 else -1
+        px = check_device_tensor(x, self.device, (B, self.N_IN), "infer_bf16_noalloc x")
+        py = check_device_tensor(out, self.device, (B, self.N_OUT), "infer_bf16_noalloc out")
+        self._check(self._lib.nfm_mlp_infer_bf16_noalloc(self.ctx, px, B, py), "infer_bf16_noalloc")
         return out
 
 
