@@ -236,6 +236,9 @@ def main():
                     help="single-size configs: speculative table lookups: -1 automatic, 0 off, 1 on")
     ap.add_argument("--ws", type=int, default=0, choices=[0, 1, 2],
                     help="single-size configs: generator wave beside each sampling wave: 0 automatic, 1 never, 2 always")
+    ap.add_argument("--tuning", default="",
+                    help="mixed configs: a fixed launch configuration 'schedule,sweeps_per_launch,waves_per_cu,speculate' "
+                         "instead of the autotuner's pick (to profile one configuration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a reference dispatch of known traffic "
@@ -267,7 +270,13 @@ def main():
     if len(mix) > 1 and not pt:
         b.run_sweeps(64)                  # one short round so that the tables have their working shape
         b.rec_update(F_TOL)
-        tuned, _ = b.autotune(calib_sweeps=256)
+        if args.tuning:
+            sch, spl, wpc, spec = (int(x) for x in args.tuning.split(","))
+            b.set_tuning(schedule=sch, sweeps_per_launch=spl, waves_per_cu=wpc, speculate=spec)
+            tuned = b.get_tuning()
+        else:
+            # calibration runs of 1024 sweeps per candidate: shorter ones rank the candidates less reliably
+            tuned, _ = b.autotune(calib_sweeps=1024)
     else:
         # 1000 sweeps per launch: the rounds of 1e4 / 1e5 sweeps split into equal launches
         b.set_tuning(speculate=args.speculate, sweeps_per_launch=min(1000, S), ws=args.ws)

@@ -422,7 +422,7 @@ nfm_status nfm_rt_stats(nfm_ctx* ctx, int32_t r0, int32_t count, uint64_t min_tr
                         nfm_rt_summary* host_summary);
 
 /* ---------------------------------------------------------------------------------------
- * Round-trip-time statistics across realizations (Sec. IV). Host functions, no context, no
+ * Round-trip-time statistics across realizations (Secs. IV and V). Host functions, no context, no
  * device: inputs are per-realization mean round-trip times (nfm_rt_stats), all finite and > 0.
  *
  * Frechet distribution, Eq. (9): F(tau) = exp(-(1 + xi (tau - mu)/beta)^(-1/xi)) on
@@ -463,6 +463,21 @@ double nfm_upper_gamma(double a, double x);
 nfm_status nfm_frechet_fit(const double* tau, int64_t n, int32_t method, nfm_frechet* fit, double* objective);
 nfm_status nfm_relative_performance(const double* tau_m, const double* tau_ref, int64_t n, double eps,
                                     int32_t method, int32_t blocks, nfm_ratio* out);
+/* nfm_frechet_fit_jackknife: the fit of nfm_frechet_fit to n >= 3 times and the delete-a-block
+ *   jackknife errors of (mu, beta, xi): the fit is repeated with each of B contiguous blocks
+ *   [b n / B, (b + 1) n / B) left out (B = n for blocks = 0, else blocks in [2, n], every subsample
+ *   keeping at least 3 times) and err^2 = (B - 1)/B sum_b (theta_b - mean theta)^2 per parameter
+ *   (Sec. IV: Fig. 4 plots the shape xi per size and method with such errors). *blocks_used (may
+ *   be NULL) receives B.
+ * nfm_running_mean: out[i] = (tau_0 + ... + tau_i) / (i + 1), the running mean of Eq. (12) (Sec. V,
+ *   plotted in Fig. 5) over the realizations in the given order, summed left to right.
+ * nfm_frechet_ks: sup over tau of |F_n(tau) - F(tau)| between the empirical CDF of the n times
+ *   and Eq. (9) with the given parameters (the fit quality behind Fig. 3), evaluated at the sorted
+ *   times from both sides of each step. */
+nfm_status nfm_frechet_fit_jackknife(const double* tau, int64_t n, int32_t method, int32_t blocks, nfm_frechet* fit,
+                                     nfm_frechet* err, int32_t* blocks_used);
+nfm_status nfm_running_mean(const double* tau, int64_t n, double* out);
+nfm_status nfm_frechet_ks(const nfm_frechet* d, const double* tau, int64_t n, double* dist);
 /* Message of the calling thread's last failed statistics call (thread-local storage). */
 const char* nfm_stats_last_error(void);
 

@@ -1,4 +1,4 @@
-"""Oracle of the round-trip-time statistics (Sec. IV): test infrastructure, not product code.
+"""Oracle of the round-trip-time statistics (Secs. IV, V): test infrastructure, not product code.
 
 Written from the definitions: the Frechet CDF of Eq. (9), its density, the distribution mean of
 Eq. (10) and the quantile mean of Eq. (14) as the integrals they are defined by (mpmath
@@ -187,3 +187,53 @@ def relative_performance(tau_m, tau_ref, eps=1e-4, method=0, blocks=0):
         return math.sqrt((B - 1) / B * float(np.sum((v - v.mean()) ** 2)))
     return {"r_pop": rp, "r_pop_err": err(jp), "r_eps": re, "r_eps_err": err(je), "fit_m": pa, "fit_ref": pb,
             "blocks": B}
+
+
+def running_mean(tau):
+    """Eq. (12): tau_bar(n) = (1/n) sum_{i=1..n} tau_i for n = 1..N, in the order given."""
+    out = []
+    s = 0.0
+    for i, t in enumerate(np.asarray(tau, dtype=np.float64)):
+        s += float(t)
+        out.append(s / (i + 1))
+    return np.array(out)
+
+
+def ks_distance(params, tau):
+    """sup over tau of |F_n(tau) - F(tau)| between the empirical CDF F_n of the sample and Eq. (9):
+    the step function F_n jumps only at the sample points, so the supremum is attained at one of
+    them, from the left (F_n = count below) or from the right (F_n = count at or below)."""
+    t = np.asarray(tau, dtype=np.float64)
+    n = len(t)
+    d = 0.0
+    for x in t:
+        below = float(np.sum(t < x)) / n
+        at_or_below = float(np.sum(t <= x)) / n
+        f = float(cdf(params, x))
+        d = max(d, abs(f - below), abs(at_or_below - f))
+    return d
+
+
+def jackknife(stat, n, blocks=0):
+    """Delete-a-block jackknife of a statistic of n ordered observations: stat(keep) is evaluated
+    on the full sample and with each of B contiguous blocks [b n / B, (b + 1) n / B) left out
+    (B = n for blocks = 0); err^2 = (B - 1)/B sum_b (theta_b - mean_b theta_b)^2, per component."""
+    B = n if blocks == 0 else blocks
+    full = np.atleast_1d(np.asarray(stat(np.ones(n, bool)), dtype=np.float64))
+    parts = []
+    for k in range(B):
+        keep = np.ones(n, bool)
+        keep[k * n // B:(k + 1) * n // B] = False
+        parts.append(np.atleast_1d(np.asarray(stat(keep), dtype=np.float64)))
+    parts = np.array(parts)
+    err = np.sqrt((B - 1) / B * np.sum((parts - parts.mean(axis=0)) ** 2, axis=0))
+    return full, err, B
+
+
+def fit_jackknife(tau, method=0, blocks=0):
+    """The Frechet fit of Eq. (9) to the sample and the jackknife errors of (mu, beta, xi) over
+    blocks of realizations (Fig. 4: the shape xi per size and method with jackknife errors)."""
+    t = np.asarray(tau, dtype=np.float64)
+    fit = fit_ml if method == 0 else fit_ls
+    full, err, B = jackknife(lambda keep: fit(t[keep])[0], len(t), blocks)
+    return tuple(float(x) for x in full), tuple(float(x) for x in err), B

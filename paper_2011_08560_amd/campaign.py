@@ -1,4 +1,4 @@
-"""Round-trip-time campaigns: the comparison of Sec. IV and the power-law parameter scan.
+"""Round-trip-time campaigns: the comparison of Secs. III-V and the power-law parameter scan.
 
 For one lattice size, a batch of disorder realizations first runs the weight iteration (flat
 target) to convergence; the converged estimate S = ln Omega then gives the production ensembles
@@ -136,8 +136,16 @@ def tempering(b, L, min_trips, chunk, cap, burn=1000, adaptive=False, log=None):
     return tau, done, e_top, extra
 
 
+RUNNING_MEAN_POINTS = (0.01, 0.03, 0.1, 0.3, 1.0)
+
+
 def analyse(taus: dict, ref="pl", eps=1e-4, blocks=0):
-    """Fits and ratios over the realizations uncensored under every method (paired)."""
+    """Fits and ratios over the realizations uncensored under every method (paired): per method
+    tau_pop, the ML fit of Eq. (9) with delete-a-block jackknife errors of its parameters (Fig. 4),
+    the distance sup |F_n - F| between the empirical and the fitted CDF (Fig. 3), the running mean
+    of Eq. (12) over the realizations in their order (Fig. 5; at fractions RUNNING_MEAN_POINTS of
+    the sample and in full), the quantile and distribution means (Eqs. (11), (14)), and the ratios
+    r of Table I against the reference method with their jackknife errors."""
     ok = np.ones(len(next(iter(taus.values()))), bool)
     for t in taus.values():
         ok &= np.isfinite(t) & (t > 0)
@@ -145,9 +153,17 @@ def analyse(taus: dict, ref="pl", eps=1e-4, blocks=0):
     for m, t in taus.items():
         tt = t[ok]
         rec = {"tau_pop": float(tt.mean()) if len(tt) else None}
+        if len(tt) >= 1:
+            run = nfm.running_mean(tt)
+            rec["running_mean"] = {f"{f:g}": float(run[max(1, int(round(f * len(tt)))) - 1])
+                                   for f in RUNNING_MEAN_POINTS}
+            rec["running_mean_series"] = [float(x) for x in run]
         if len(tt) >= 3:
-            fit, _ = nfm.frechet_fit(tt, 0)
+            B = blocks if blocks and len(tt) - (len(tt) + blocks - 1) // blocks >= 3 else 0
+            fit, err, used = nfm.frechet_fit_jackknife(tt, 0, B)
             rec.update({"frechet": {"mu": fit[0], "beta": fit[1], "xi": fit[2]},
+                        "frechet_err": {"mu": err[0], "beta": err[1], "xi": err[2], "blocks": used},
+                        "ks_distance": nfm.frechet_ks(fit, tt),
                         "quantile_mean": nfm.frechet_quantile_mean(fit, eps),
                         "mean": nfm.frechet_mean(fit), "median": float(np.median(tt))})
             if m != ref and ref in taus:
@@ -160,7 +176,8 @@ def analyse(taus: dict, ref="pl", eps=1e-4, blocks=0):
 
 def compare(L, n_real, methods=METHODS, min_trips=100, iter_sweeps=None, f_tol=0.5, n_max=60, chunk=None,
             cap=None, first_id=0, eps=1e-4, blocks=0, log=None):
-    """The comparison of Sec. IV at one L; returns a JSON-able record."""
+    """The comparison of Secs. III-V at one L (round trips of every method, their distributions
+    and Table I's ratios); returns a JSON-able record."""
     iter_sweeps = iter_sweeps or 1000 * L * L
     chunk = chunk or 50 * L ** 3
     cap = cap or 1000 * chunk
@@ -339,18 +356,38 @@ def main(argv=None):
     t0 = time.time()
     log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
     if args.analyse:
-        taus, cap = {}, {}
+        # files of one size pool their methods; files of several sizes give one analysis per size
+        groups = {}
         for path in args.analyse:
             with np.load(path, allow_pickle=False) as z:
+                L = int(z["L"]) if "L" in z.files else None
+                g = groups.setdefault(L, {"sources": [], "taus": {}, "cap": {}})
+                g["sources"].append(path)
                 for k in z.files:
                     if k.startswith("tau_"):
-                        taus[k[4:]] = z[k]
+                        g["taus"][k[4:]] = z[k]
                     elif k.startswith("sweeps_"):
-                        cap[k[7:]] = int(z[k])
-        rec = {"sources": args.analyse, "sweeps_run": cap,
-               "censored": {m: int((~np.isfinite(t)).sum()) for m, t in taus.items()},
-               "analysis": analyse(taus, eps=args.eps, blocks=args.blocks)}
-        print(json.dumps(rec), flush=True)
+                        g["cap"][k[7:]] = int(z[k])
+        recs = {}
+        for L, g in groups.items():
+            recs[L] = {"sources": g["sources"], "sweeps_run": g["cap"],
+                       "censored": {m: int((~np.isfinite(t)).sum()) for m, t in g["taus"].items()},
+                       "analysis": analyse(g["taus"], eps=args.eps, blocks=args.blocks)}
+        for L, r in sorted(recs.items(), key=lambda kv: (kv[0] is None, kv[0] or 0)):
+            for m, a in r["analysis"]["methods"].items():
+                if "frechet" not in a:
+                    continue
+                rr = a.get("r", {})
+                print(f"L={L} {m:12s} xi = {a['frechet']['xi']:.3f} +- {a['frechet_err']['xi']:.3f}  "
+                      f"KS = {a['ks_distance']:.3f}  tau_pop = {a['tau_pop']:.4g}  running mean at n/10, n: "
+                      f"{a['running_mean']['0.1']:.4g}, {a['running_mean']['1']:.4g}"
+                      + (f"  r_pop = {rr['r_pop']:.3f}({rr['r_pop_err']:.3f}) r_eps = {rr['r_eps']:.3f}"
+                         f"({rr['r_eps_err']:.3f})" if rr else ""), file=sys.stderr, flush=True)
+        if len(recs) == 1:
+            out = next(iter(recs.values()))
+        else:
+            out = {"by_L": {str(L): r for L, r in recs.items()}}
+        print(json.dumps(out), flush=True)
         return
     for L in args.L:
         if args.estimators:
@@ -373,7 +410,7 @@ def main(argv=None):
             if args.save_tau:
                 np.savez(args.save_tau, **{f"tau_{m}": np.array([np.nan if x is None else x for x in t], float)
                                           for m, t in tau.items()},
-                         **{f"sweeps_{m}": np.int64(v) for m, v in rec["sweeps_run"].items()})
+                         **{f"sweeps_{m}": np.int64(v) for m, v in rec["sweeps_run"].items()}, L=np.int64(L))
         rec["wall_s"] = time.time() - t0
         print(json.dumps(rec), flush=True)
 

@@ -1,8 +1,10 @@
-// Round-trip-time statistics across disorder realizations (Sec. IV): the Frechet form of the
+// Round-trip-time statistics across disorder realizations (Secs. IV, V): the Frechet form of the
 // distribution of the realizations' mean round-trip times, Eq. (9); its mean, Eq. (11); the
 // quantile function, Eq. (13); the quantile mean, Eq. (14), in closed form; fits of the three
-// parameters to measured times; and the relative performance of two methods with
-// delete-a-block jackknife errors. Host code only: a few thousand numbers per fit.
+// parameters to measured times, with delete-a-block jackknife errors (the shape per size and
+// method, Fig. 4); the distance between the empirical and the fitted distribution (Fig. 3); the
+// running mean of Eq. (12) (Fig. 5); and the relative performance of two methods with
+// delete-a-block jackknife errors (Sec. V, Table I). Host code only: a few thousand numbers per fit.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -423,6 +425,71 @@ nfm_status nfm_relative_performance(const double* tau_m, const double* tau_ref, 
   };
   *out = nfm_ratio{rp, jk_err(jp), re, jk_err(je), nfm_frechet{fm.mu, fm.beta, fm.xi},
                    nfm_frechet{fr.mu, fr.beta, fr.xi}, (int32_t)B, 0};
+  return NFM_OK;
+}
+
+nfm_status nfm_frechet_fit_jackknife(const double* tau, int64_t n, int32_t method, int32_t blocks, nfm_frechet* fit_out,
+                                     nfm_frechet* err_out, int32_t* blocks_used) {
+  if (!fit_out || !err_out) return fail("frechet_fit_jackknife: null output");
+  if (!valid_sample(tau, n)) return fail("frechet_fit_jackknife: need n >= 3 finite positive times");
+  if (method != 0 && method != 1) return fail("frechet_fit_jackknife: method must be 0 (ML) or 1 (least squares)");
+  const int64_t B = blocks == 0 ? n : blocks;
+  if (B < 2 || B > n) return fail("frechet_fit_jackknife: blocks must be 0 (one per realization) or in [2, n]");
+  if (n - (n + B - 1) / B < 3) return fail("frechet_fit_jackknife: a subsample would hold fewer than 3 times");
+  auto estimate = [&](int64_t skip_lo, int64_t skip_hi, Params* out) {
+    std::vector<double> a;
+    a.reserve(n);
+    for (int64_t i = 0; i < n; ++i)
+      if (i < skip_lo || i >= skip_hi) a.push_back(tau[i]);
+    std::sort(a.begin(), a.end());
+    double obj;
+    *out = fit(a, method, &obj);
+    return std::isfinite(obj);
+  };
+  Params full;
+  if (!estimate(0, 0, &full)) return fail("frechet_fit_jackknife: fit failed on the full sample");
+  std::vector<Params> part(B);
+  for (int64_t k = 0; k < B; ++k)
+    if (!estimate(k * n / B, (k + 1) * n / B, &part[k])) return fail("frechet_fit_jackknife: fit failed on a subsample");
+  auto jk_err = [&](double Params::*f) {
+    double m = 0.0;
+    for (const auto& q : part) m += q.*f;
+    m /= (double)B;
+    double s = 0.0;
+    for (const auto& q : part) s += (q.*f - m) * (q.*f - m);
+    return std::sqrt((double)(B - 1) / (double)B * s);
+  };
+  *fit_out = nfm_frechet{full.mu, full.beta, full.xi};
+  *err_out = nfm_frechet{jk_err(&Params::mu), jk_err(&Params::beta), jk_err(&Params::xi)};
+  if (blocks_used) *blocks_used = (int32_t)B;
+  return NFM_OK;
+}
+
+nfm_status nfm_running_mean(const double* tau, int64_t n, double* out) {
+  if (!tau || !out || n < 1) return fail("running_mean: need n >= 1 and both arrays");
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    s += tau[i];
+    out[i] = s / (double)(i + 1);
+  }
+  return NFM_OK;
+}
+
+nfm_status nfm_frechet_ks(const nfm_frechet* d, const double* tau, int64_t n, double* dist) {
+  if (!d || !tau || !dist || n < 1) return fail("frechet_ks: need a distribution, n >= 1 times and an output");
+  if (!(d->beta > 0.0) || !(d->xi > 0.0)) return fail("frechet_ks: beta > 0 and xi > 0");
+  std::vector<double> s(tau, tau + n);
+  for (double x : s)
+    if (!std::isfinite(x)) return fail("frechet_ks: times must be finite");
+  std::sort(s.begin(), s.end());
+  const Params p{d->mu, d->beta, d->xi};
+  double D = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double F = cdf(p, s[i]);
+    // the empirical CDF is i/n just below the i-th smallest time and (i+1)/n at it
+    D = std::max(D, std::max(F - (double)i / (double)n, (double)(i + 1) / (double)n - F));
+  }
+  *dist = D;
   return NFM_OK;
 }
 

@@ -176,6 +176,10 @@ def lib():
         "nfm_upper_gamma": (dbl, [dbl, dbl]),
         "nfm_frechet_fit": (i32, [vp, i64, i32, C.POINTER(Frechet), C.POINTER(dbl)]),
         "nfm_relative_performance": (i32, [vp, vp, i64, dbl, i32, i32, C.POINTER(Ratio)]),
+        "nfm_frechet_fit_jackknife": (i32, [vp, i64, i32, i32, C.POINTER(Frechet), C.POINTER(Frechet),
+                                            C.POINTER(i32)]),
+        "nfm_running_mean": (i32, [vp, i64, vp]),
+        "nfm_frechet_ks": (i32, [C.POINTER(Frechet), vp, i64, C.POINTER(dbl)]),
         "nfm_stats_last_error": (C.c_char_p, []),
     })
     f32 = C.c_float
@@ -773,7 +777,7 @@ class Mlp:
 
 
 # --------------------------------------------------------------------------- round-trip statistics
-# Host functions of the library (Sec. IV); times are per-realization mean round-trip times.
+# Host functions of the library (Secs. IV, V); times are per-realization mean round-trip times.
 
 def _frechet(params) -> Frechet:
     mu, beta, xi = params
@@ -832,3 +836,35 @@ def relative_performance(tau_m, tau_ref, eps: float = 1e-4, method: int = 0, blo
         raise NfmError(st, "relative_performance: " + lib().nfm_stats_last_error().decode())
     return {"r_pop": out.r_pop, "r_pop_err": out.r_pop_err, "r_eps": out.r_eps, "r_eps_err": out.r_eps_err,
             "fit_m": out.fit_m.as_tuple(), "fit_ref": out.fit_ref.as_tuple(), "blocks": out.blocks}
+
+
+def frechet_fit_jackknife(tau, method: int = 0, blocks: int = 0):
+    """Fit of Eq. (9) and the delete-a-block jackknife errors of its parameters (Fig. 4: the shape
+    xi with jackknife errors). Returns ((mu, beta, xi), (err_mu, err_beta, err_xi), blocks)."""
+    t = _times(tau)
+    fit, err, B = Frechet(), Frechet(), C.c_int32()
+    st = lib().nfm_frechet_fit_jackknife(t.ctypes.data, len(t), int(method), int(blocks), C.byref(fit), C.byref(err),
+                                         C.byref(B))
+    if st != 0:
+        raise NfmError(st, "frechet_fit_jackknife: " + lib().nfm_stats_last_error().decode())
+    return fit.as_tuple(), err.as_tuple(), B.value
+
+
+def running_mean(tau) -> np.ndarray:
+    """Eq. (12) over the realizations in the given order: out[i] = mean of tau[0..i]."""
+    t = _times(tau)
+    out = np.zeros(len(t), np.float64)
+    st = lib().nfm_running_mean(t.ctypes.data, len(t), out.ctypes.data)
+    if st != 0:
+        raise NfmError(st, "running_mean: " + lib().nfm_stats_last_error().decode())
+    return out
+
+
+def frechet_ks(params, tau) -> float:
+    """sup |F_n - F| between the empirical CDF of the times and Eq. (9) with these parameters."""
+    t = _times(tau)
+    d = C.c_double()
+    st = lib().nfm_frechet_ks(C.byref(_frechet(params)), t.ctypes.data, len(t), C.byref(d))
+    if st != 0:
+        raise NfmError(st, "frechet_ks: " + lib().nfm_stats_last_error().decode())
+    return d.value

@@ -1,6 +1,8 @@
 """The host-side pooling of saved round-trip times (campaign --analyse): methods from several
 files of the same realizations, censored entries (NaN) leaving every method's sample, and the
-relative performance against the power law as the oracle computes it on the paired sample."""
+relative performance against the power law as the oracle computes it on the paired sample, the
+jackknife errors of the fitted shape, the distance of the empirical CDF from the fit and the
+running mean of Eq. (12); files of several sizes give one analysis per size."""
 import json
 import os
 import subprocess
@@ -41,3 +43,33 @@ def test_analyse_pools_saved_methods(tmp_path):
         assert got["r_pop_err"] == pytest.approx(want["r_pop_err"], rel=1e-9)
         assert got["r_eps"] == pytest.approx(want["r_eps"], rel=1e-4)
     assert rec["analysis"]["methods"]["pl"]["tau_pop"] == pytest.approx(float(pl[ok].mean()), rel=1e-12)
+    a_pl = rec["analysis"]["methods"]["pl"]
+    fit, err, B = S.fit_jackknife(pl[ok], 0, 8)
+    assert a_pl["frechet_err"]["blocks"] == 8
+    assert a_pl["frechet"]["xi"] == pytest.approx(fit[2], rel=1e-4)
+    assert a_pl["frechet_err"]["xi"] == pytest.approx(err[2], rel=5e-3)
+    assert a_pl["ks_distance"] == pytest.approx(S.ks_distance(tuple(a_pl["frechet"][k] for k in ("mu", "beta", "xi")),
+                                                              pl[ok]), rel=1e-12)
+    run = S.running_mean(pl[ok])
+    assert np.allclose(a_pl["running_mean_series"], run, rtol=1e-14, atol=0)
+    assert a_pl["running_mean"]["1"] == pytest.approx(float(pl[ok].mean()), rel=1e-12)
+
+
+def test_analyse_groups_files_by_size(tmp_path):
+    rng = np.random.default_rng(6)
+    files = []
+    for L, xi in ((4, 0.4), (6, 0.9)):
+        pl = sst.genextreme(-xi, loc=100.0 * L, scale=30.0 * L).rvs(24, random_state=rng)
+        flat = 2.0 * pl
+        f = tmp_path / f"L{L}.npz"
+        np.savez(f, tau_pl=pl, tau_flat=flat, sweeps_pl=np.int64(10), sweeps_flat=np.int64(20), L=np.int64(L))
+        files.append(str(f))
+    out = subprocess.run([sys.executable, "-m", "paper_2011_08560_amd.campaign", "--analyse", *files, "--blocks", "4"],
+                         capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    rec = json.loads(out.stdout)
+    assert sorted(rec["by_L"]) == ["4", "6"]
+    for L in ("4", "6"):
+        r = rec["by_L"][L]["analysis"]["methods"]["flat"]["r"]
+        assert r["r_pop"] == pytest.approx(2.0, rel=1e-12)
+    assert "xi = " in out.stderr and "L=6" in out.stderr

@@ -1,4 +1,4 @@
-"""The round-trip-time comparison of Sec. IV at test scale (L = 4, 64 realizations), end to end on
+"""The round-trip-time comparison of Secs. III-V at test scale (L = 4, 64 realizations), end to end on
 the GPU: weight iteration, the flat / 1/k / power-law production ensembles and parallel tempering
 run until every realization has its round trips, then the host statistics of the library
 (Frechet fits, quantile means, ratios with jackknife errors).

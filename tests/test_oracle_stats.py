@@ -1,4 +1,4 @@
-"""Pins of the round-trip-time statistics oracle (Sec. IV) against facts outside it.
+"""Pins of the round-trip-time statistics oracle (Secs. IV, V) against facts outside it.
 
 * Eq. (9) against scipy's generalized extreme value distribution (shape c = -xi), an independent
   implementation: CDF, density, quantiles, mean;

@@ -1,4 +1,4 @@
-"""Parity of the library's round-trip statistics (host code in libnfm, Sec. IV) with the oracle.
+"""Parity of the library's round-trip statistics (host code in libnfm, Secs. IV, V) with the oracle.
 
 These functions run on the host, so they are checked on the CPU: the closed forms against the
 oracle's quadratures, the incomplete gamma function against mpmath, the fits against the
@@ -113,3 +113,29 @@ def test_quantile_mean_near_the_gumbel_limit(nfm, xi):
     params = (184.76, 35.5, xi)
     for eps in (0.0, 1e-4, 0.3, 0.9):
         assert nfm.frechet_quantile_mean(params, eps) == pytest.approx(S.quantile_mean(params, eps), rel=1e-13)
+
+
+@pytest.mark.parametrize("blocks", [0, 6])
+def test_fit_jackknife_matches_oracle(nfm, blocks):
+    n = 18 if blocks == 0 else 42
+    t = _times((400.0, 120.0, 0.7), n, 11)
+    fit, err, B = nfm.frechet_fit_jackknife(t, 0, blocks)
+    wfit, werr, wB = S.fit_jackknife(t, 0, blocks)
+    assert B == wB == (n if blocks == 0 else blocks)
+    for g, w in zip(fit, wfit):
+        assert g == pytest.approx(w, rel=2e-5)
+    for g, w in zip(err, werr):
+        assert g == pytest.approx(w, rel=2e-3, abs=1e-6 * max(abs(v) for v in wfit))
+    with pytest.raises(nfm.NfmError):
+        nfm.frechet_fit_jackknife(t[:4], 0, 2)        # a subsample of 2 times cannot be fitted
+
+
+def test_running_mean_and_ks_match_oracle(nfm):
+    t = _times((50.0, 20.0, 1.2), 300, 12)
+    assert np.allclose(nfm.running_mean(t), S.running_mean(t), rtol=1e-14, atol=0)
+    for params in ((50.0, 20.0, 1.2), (45.0, 25.0, 0.9)):
+        assert nfm.frechet_ks(params, t) == pytest.approx(S.ks_distance(params, t), rel=1e-12, abs=1e-15)
+    tt = np.concatenate([t[:7], t[:7], t[3:9]])      # ties
+    assert nfm.frechet_ks((50.0, 20.0, 1.2), tt) == pytest.approx(S.ks_distance((50.0, 20.0, 1.2), tt), rel=1e-12)
+    with pytest.raises(nfm.NfmError):
+        nfm.frechet_ks((50.0, -1.0, 1.2), t)
