@@ -212,8 +212,11 @@ def lib():
 
 def _desc(Ls: Sequence[int], walkers: Sequence[int], disorder_seed: int, walker_seed: int,
           first_real_id: int, trace_capacity: int):
-    La = np.ascontiguousarray(Ls, np.int32)
-    Wa = np.ascontiguousarray(walkers, np.int32)
+    La = np.ascontiguousarray(Ls, np.int32).reshape(-1)
+    Wa = np.ascontiguousarray(walkers, np.int32).reshape(-1)
+    if len(La) != len(Wa):
+        # the library reads n_real entries of both arrays: refuse before it reads past one
+        raise NfmError(NFM_EINVAL, f"batch description: {len(La)} sizes but {len(Wa)} walker counts")
     d = BatchDesc(len(La), La.ctypes.data_as(C.POINTER(C.c_int32)), Wa.ctypes.data_as(C.POINTER(C.c_int32)),
                   disorder_seed, walker_seed, first_real_id, trace_capacity)
     return d, (La, Wa)
