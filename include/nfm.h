@@ -191,10 +191,20 @@ nfm_status nfm_read_histograms(nfm_ctx* ctx, uint64_t* host_dst, int reset);
 nfm_status nfm_reset_histograms(nfm_ctx* ctx);
 nfm_status nfm_read_walkers(nfm_ctx* ctx, nfm_walker_stats* host_dst);   /* all walkers */
 nfm_status nfm_read_realizations(nfm_ctx* ctx, nfm_real_stats* host_dst); /* all realizations */
-/* Trace: walkers x trace_capacity int32 (walker-major); entry s is the energy
- * after the s-th traced sweep; *n_valid receives the number of traced sweeps. */
+/* Trace: the traced walkers x capacity int32 (walker-major); entry s of a walker is its energy
+ * after the s-th traced sweep; *n_valid receives the number of traced sweeps. By default every
+ * walker of the batch is traced with capacity = the description's trace_capacity.
+ * nfm_reset_trace restarts the trace at the current sweep.
+ * nfm_trace_config traces the walkers [walker_begin, walker_begin + count) (global indices) for up
+ * to `capacity` sweeps each, from the current sweep on (Sec. III's energy traces of chosen
+ * walkers at a longer horizon): NFM_EINVAL unless the range lies in the batch and capacity >= 0,
+ * NFM_ESIZE if count x capacity exceeds the trace region the workspace holds (all walkers x
+ * trace_capacity). nfm_read_trace then copies count x capacity entries. Checkpoints keep it. */
 nfm_status nfm_read_trace(nfm_ctx* ctx, int32_t* host_dst, int32_t* n_valid);
 nfm_status nfm_reset_trace(nfm_ctx* ctx);
+nfm_status nfm_trace_config(nfm_ctx* ctx, int64_t walker_begin, int64_t count, int32_t capacity);
+/* The traced range and capacity in effect (host-side, no synchronization). */
+nfm_status nfm_trace_range(const nfm_ctx* ctx, int64_t* walker_begin, int64_t* count, int32_t* capacity);
 
 /* Inject histograms (nfm_levels_total() uint64, same layout as nfm_read_histograms). */
 nfm_status nfm_set_histograms(nfm_ctx* ctx, const uint64_t* host_src);

@@ -127,7 +127,9 @@ struct nfm_ctx {
   Layout lay{};
   int n_real = 0;
   uint64_t disorder_seed = 0, walker_seed = 0;
-  int trace_cap = 0;
+  int trace_cap = 0;                       // sweeps traced per walker of the traced range
+  int64_t trace_slots = 0;                 // int32 entries of the workspace's trace region
+  int64_t trace_w0 = 0, trace_nw = 0;      // traced walkers [trace_w0, trace_w0 + trace_nw)
   uint64_t sweeps = 0, trace_t0 = 0;
   bool couplings = false;
   int speculate = -1;                      // -1 auto, 0 off, 1 on
@@ -286,6 +288,9 @@ nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_works
     c->disorder_seed = desc->disorder_seed;
     c->walker_seed = desc->walker_seed;
     c->trace_cap = desc->trace_capacity;
+    c->trace_slots = l.total_walkers * (int64_t)desc->trace_capacity;
+    c->trace_w0 = 0;
+    c->trace_nw = l.total_walkers;
     c->reals.resize(desc->n_real);
     int64_t woff = 0, soff = 0, loff = 0, toff = 0, jaoff = 0, jkoff = 0;
     for (int r = 0; r < desc->n_real; ++r) {
@@ -570,6 +575,8 @@ static nfm::SweepArgs muca_args(nfm_ctx* c, uint64_t t0, uint32_t n, int trace_c
   a.trace = c->d_trace();
   a.trace_cap = trace_cap;
   a.trace_t0 = c->trace_t0;
+  a.trace_w0 = c->trace_w0;
+  a.trace_nw = c->trace_nw;
   a.t0 = t0;
   a.n_sweeps = n;
   a.walker_seed = c->walker_seed;
@@ -690,9 +697,9 @@ nfm_status nfm_read_trace(nfm_ctx* c, int32_t* host_dst, int32_t* n_valid) {
   if (!n_valid) return fail(c, NFM_EINVAL, "read_trace: null pointer");
   const uint64_t done = c->sweeps - c->trace_t0;
   *n_valid = (int32_t)std::min<uint64_t>(done, (uint64_t)c->trace_cap);
-  if (c->trace_cap > 0) {
+  if (c->trace_cap > 0 && c->trace_nw > 0) {
     if (!host_dst) return fail(c, NFM_EINVAL, "read_trace: null pointer");
-    NFM_HIP(c, hipMemcpyAsync(host_dst, c->d_trace(), 4 * (size_t)c->lay.total_walkers * c->trace_cap,
+    NFM_HIP(c, hipMemcpyAsync(host_dst, c->d_trace(), 4 * (size_t)c->trace_nw * c->trace_cap,
                               hipMemcpyDeviceToHost, c->stream));
     NFM_HIP(c, hipStreamSynchronize(c->stream));
   }
@@ -701,6 +708,29 @@ nfm_status nfm_read_trace(nfm_ctx* c, int32_t* host_dst, int32_t* n_valid) {
 
 nfm_status nfm_reset_trace(nfm_ctx* c) {
   NFM_GUARD(c);
+  c->trace_t0 = c->sweeps;
+  return NFM_OK;
+}
+
+nfm_status nfm_trace_range(const nfm_ctx* c, int64_t* walker_begin, int64_t* count, int32_t* capacity) {
+  if (!c || !walker_begin || !count || !capacity) return NFM_EINVAL;
+  *walker_begin = c->trace_w0;
+  *count = c->trace_nw;
+  *capacity = c->trace_cap;
+  return NFM_OK;
+}
+
+nfm_status nfm_trace_config(nfm_ctx* c, int64_t walker_begin, int64_t count, int32_t capacity) {
+  NFM_GUARD(c);
+  if (walker_begin < 0 || count < 0 || capacity < 0 || walker_begin > c->lay.total_walkers ||
+      count > c->lay.total_walkers - walker_begin)
+    return fail(c, NFM_EINVAL, "trace_config: walkers [begin, begin + count) must lie in the batch, capacity >= 0");
+  if (count > 0 && capacity > 0 && count > c->trace_slots / capacity)
+    return fail(c, NFM_ESIZE, "trace_config: count x capacity exceeds the trace the workspace holds (" +
+                                  std::to_string(c->trace_slots) + " entries)");
+  c->trace_w0 = walker_begin;
+  c->trace_nw = count;
+  c->trace_cap = (count > 0) ? capacity : 0;
   c->trace_t0 = c->sweeps;
   return NFM_OK;
 }
@@ -719,7 +749,7 @@ nfm_status nfm_sync(nfm_ctx* c) {
 // holds offsets, not addresses, so the copy is valid at any workspace address).
 namespace {
 constexpr char kCkptMagic[8] = {'N', 'F', 'M', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t kCkptVersion = 2;   // 2: the tuning's generator-wave mode is part of the header
+constexpr uint32_t kCkptVersion = 3;   // 3: the traced walker range is part of the header
 struct CkptHeader {
   char magic[8];
   uint32_t version, n_real;
@@ -728,6 +758,7 @@ struct CkptHeader {
   uint32_t sweeps_per_launch;
   int32_t schedule, waves_per_cu, rec_ready, pt_M, wl_ready;
   uint64_t sweeps, trace_t0, pt_t_reset;
+  int64_t trace_slots, trace_w0, trace_nw;
 };
 
 // FNV-1a over every realization's size, walker count and id: the layout of the workspace
@@ -784,6 +815,9 @@ nfm_status nfm_checkpoint(nfm_ctx* c, void* host_blob, size_t capacity) {
   h.sweeps = c->sweeps;
   h.trace_t0 = c->trace_t0;
   h.pt_t_reset = c->pt_t_reset;
+  h.trace_slots = c->trace_slots;
+  h.trace_w0 = c->trace_w0;
+  h.trace_nw = c->trace_nw;
   char* out = (char*)host_blob;
   std::memcpy(out, &h, sizeof(h));
   double* T = (double*)(out + sizeof(h));
@@ -804,11 +838,14 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
   if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion)
     return fail(c, NFM_EINVAL, "restore: not a checkpoint of this library version");
   if (h.n_real != (uint32_t)c->n_real || h.batch_hash != batch_hash(c) || h.workspace_bytes != c->lay.total ||
-      h.disorder_seed != c->disorder_seed || h.walker_seed != c->walker_seed || h.trace_cap != c->trace_cap)
+      h.disorder_seed != c->disorder_seed || h.walker_seed != c->walker_seed || h.trace_slots != c->trace_slots)
     return fail(c, NFM_EINVAL, "restore: checkpoint of a different batch (sizes, walkers, ids, seeds or trace)");
   if (size < ckpt_bytes(c)) return fail(c, NFM_ESIZE, "restore: checkpoint truncated");
   if (h.sweeps > (uint64_t)UINT32_MAX || h.trace_t0 > h.sweeps || h.pt_t_reset > h.sweeps)
     return fail(c, NFM_EINVAL, "restore: sweep counters out of range");
+  if (h.trace_w0 < 0 || h.trace_nw < 0 || h.trace_w0 + h.trace_nw > c->lay.total_walkers || h.trace_cap < 0 ||
+      (h.trace_nw > 0 && h.trace_cap > 0 && h.trace_nw > h.trace_slots / h.trace_cap))
+    return fail(c, NFM_EINVAL, "restore: traced walker range out of range");
   NFM_TRY(c, {
     const char* in = (const char*)host_blob;
     const size_t nT = (size_t)c->n_real * nfm::kMaxReplicas;
@@ -829,6 +866,9 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
     c->wl_ready = h.wl_ready != 0;
     c->sweeps = h.sweeps;
     c->trace_t0 = h.trace_t0;
+    c->trace_cap = h.trace_cap;
+    c->trace_w0 = h.trace_w0;
+    c->trace_nw = h.trace_nw;
     c->pt_t_reset = h.pt_t_reset;
     return pull_reals(c);   // table rows, bounds and energies base as the checkpoint had them
   })
@@ -1356,6 +1396,8 @@ nfm_status nfm_pt_run_sweeps(nfm_ctx* c, uint64_t n_sweeps) {
       a.trace = c->d_trace();
       a.trace_cap = c->trace_cap;
       a.trace_t0 = c->trace_t0;
+      a.trace_w0 = c->trace_w0;
+      a.trace_nw = c->trace_nw;
       a.t0 = c->sweeps + done;
       a.n_sweeps = chunk;
       a.walker_seed = c->walker_seed;

@@ -62,12 +62,13 @@ struct SweepArgs {
   const uint32_t* tables;
   WalkerState ws;
   unsigned long long* hist;
-  int32_t* trace;
+  int32_t* trace;             // [trace_nw][trace_cap] int32, walkers trace_w0 .. trace_w0 + trace_nw - 1
   int32_t trace_cap;
   // on-chip histogram window of a realization: levels [max(0, row0 - hist_margin), + hist_n);
   // counts outside it go to HBM directly
   int32_t hist_margin;
   uint64_t trace_t0;         // first traced sweep
+  int64_t trace_w0, trace_nw; // traced walkers (global indices)
   uint64_t t0;               // first sweep of this launch
   uint32_t n_sweeps;
   int32_t hist_n;

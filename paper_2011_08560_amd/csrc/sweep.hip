@@ -707,7 +707,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
       const int M = A.pt_M;
       const bool active = pt_active;
       if (active) track_energy(te, E, (t + 1u) * (uint64_t)N, e_bot, e_top);
-      if (t - A.trace_t0 < (uint64_t)A.trace_cap) A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = E;
+      if (t - A.trace_t0 < (uint64_t)A.trace_cap && (uint64_t)(gw - A.trace_w0) < (uint64_t)A.trace_nw)
+        A.trace[(gw - A.trace_w0) * A.trace_cap + (int64_t)(t - A.trace_t0)] = E;
       // exchange phase: slots (s, s+1), s = t (mod 2), of each set of M lanes
       const uint32_t base = pt_base;
       lds_store_i32(sE + 4u * (base + (uint32_t)slot), E);
@@ -748,8 +749,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       else if ((uint32_t)k < (uint32_t)K)  // always true for exact energies
         atomicAdd(A.hist + RI.level_off + k, 1ULL);
-      if (t - A.trace_t0 < (uint64_t)A.trace_cap)
-        A.trace[gw * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
+      if (t - A.trace_t0 < (uint64_t)A.trace_cap && (uint64_t)(gw - A.trace_w0) < (uint64_t)A.trace_nw)
+        A.trace[(gw - A.trace_w0) * A.trace_cap + (int64_t)(t - A.trace_t0)] = e_base + 4 * k;
     }
   }
 

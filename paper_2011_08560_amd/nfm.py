@@ -131,6 +131,8 @@ def lib():
         "nfm_read_realizations": (i32, [vp, vp]),
         "nfm_read_trace": (i32, [vp, vp, C.POINTER(i32)]),
         "nfm_reset_trace": (i32, [vp]),
+        "nfm_trace_config": (i32, [vp, i64, i64, i32]),
+        "nfm_trace_range": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),
         "nfm_sync": (i32, [vp]),
         "nfm_checkpoint_bytes": (i32, [vp, C.POINTER(sz)]),
         "nfm_last_kernel": (C.c_char_p, [vp]),
@@ -425,9 +427,21 @@ class Batch:
         self._check(self._lib.nfm_read_realizations(self.ctx, out.ctypes.data), "read_realizations")
         return out
 
+    def trace_range(self):
+        """(first walker, walkers, capacity) of the trace in effect."""
+        w0, nw, cap = C.c_int64(), C.c_int64(), C.c_int32()
+        self._check(self._lib.nfm_trace_range(self.ctx, C.byref(w0), C.byref(nw), C.byref(cap)), "trace_range")
+        return w0.value, nw.value, cap.value
+
+    def trace_config(self, walker_begin: int, count: int, capacity: int):
+        """Trace walkers [walker_begin, walker_begin + count) for up to `capacity` sweeps from now on."""
+        self._check(self._lib.nfm_trace_config(self.ctx, int(walker_begin), int(count), int(capacity)), "trace_config")
+
     def read_trace(self):
+        """The traced walkers' energies, [walkers of the traced range, sweeps traced so far]."""
         n = C.c_int32()
-        out = np.zeros((self.n_walkers, max(self.trace_capacity, 0)), np.int32)
+        _, nw, cap = self.trace_range()
+        out = np.zeros((nw, max(cap, 0)), np.int32)
         self._check(self._lib.nfm_read_trace(self.ctx, out.ctypes.data if out.size else None, C.byref(n)),
                     "read_trace")
         return out[:, :n.value]

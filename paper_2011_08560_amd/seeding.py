@@ -171,22 +171,43 @@ def infer(mlp, x):
     return out
 
 
-def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID, log=None):
+CANON_SWEEPS = 100 + 1000   # the canonical run behind the features: burn-in and measured sweeps
+
+
+def run_arm(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID, log=None):
+    """One arm of the paired comparison on fresh realizations: the same seeds and the same
+    canonical run for both; mlp = None runs the plain start, else the network's seed. Returns the
+    round of first convergence per realization (n_max + 1 = censored), the seed's lowest level
+    (-1 = plain start or rejected seed), the final lowest level k_lo and the final estimate as
+    the training targets would see it (y = S/N on the 256-point grid and its mask)."""
+    b = make_batch([L] * n_real, first_real_id=first_id)
+    x = canonical_features(b)
+    if mlp is None:
+        k_seed = np.full(n_real, -1, np.int64)
+        it = iterate(b, n_sweeps, f_tol, n_max, log=log)
+    else:
+        mlp.to_bf16()
+        curves = infer(mlp, x)
+        b.rec_init(0, 1.0, 0.0)
+        k_seed = np.asarray(b.rec_seed_grid(curves), np.int64)
+        it = iterate(b, n_sweeps, f_tol, n_max, initialized=True, log=log)
+    info = b.rec_read_info()
+    y, m = b.rec_targets()
+    out = {"rounds": it, "k_seed": k_seed, "k_lo": np.asarray(info["k_lo"], np.int64),
+           "y": y.cpu().numpy(), "mask": m.cpu().numpy()}
+    b.close()
+    return out
+
+
+def evaluate(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id=EVAL_FIRST_ID, log=None, full=False):
     """Paired comparison on fresh realizations: the same seeds, the same canonical run, then the
-    plain start against the seeded one. Returns the rounds to converge of both arms."""
-    plain = make_batch([L] * n_real, first_real_id=first_id)
-    seeded = make_batch([L] * n_real, first_real_id=first_id)
-    canonical_features(plain)
-    x = canonical_features(seeded)
-    mlp.to_bf16()
-    curves = infer(mlp, x)
-    seeded.rec_init(0, 1.0, 0.0)
-    k_seed = seeded.rec_seed_grid(curves)
-    it_plain = iterate(plain, n_sweeps, f_tol, n_max, log=log)
-    it_seed = iterate(seeded, n_sweeps, f_tol, n_max, initialized=True, log=log)
-    plain.close()
-    seeded.close()
-    return it_plain, it_seed, k_seed
+    plain start against the seeded one. Returns the rounds to converge of both arms (and, with
+    full=True, both arms' records of run_arm)."""
+    plain = run_arm(None, L, n_real, n_sweeps, f_tol, n_max, first_id, log)
+    seeded = run_arm(mlp, L, n_real, n_sweeps, f_tol, n_max, first_id, log)
+    if full:
+        return plain, seeded
+    return plain["rounds"], seeded["rounds"], seeded["k_seed"]
 
 
 def bench_net(batch=256, steps=200, n_infer=16384, seed=7):
@@ -236,6 +257,54 @@ def summary(it_plain, it_seed, k_seed, n_max):
             "paired_mean_gain": float((it_plain - it_seed).mean())}
 
 
+def paired_report(plain, seeded, L, n_sweeps, n_max, therm=0.1):
+    """The paired comparison at equal final flatness tolerance: rounds and total sweeps to the first
+    converged round (a round is therm * n_sweeps thermalization plus n_sweeps measured sweeps; the
+    seeded arm also pays the canonical run behind its features), censored counts, and whether the
+    two arms reached the same estimate where both converged -- the same lowest level and the same
+    S(E) within the estimates' noise (max |delta S| over the grid points both masks cover)."""
+    N = L ** 3
+    per_round = n_sweeps * (1.0 + therm)
+
+    def arm(rec, extra):
+        it = np.asarray(rec["rounds"])
+        ok = it <= n_max
+        tot = it * per_round + extra
+        q = lambda v, p: float(np.quantile(v, p)) if len(v) else None
+        return {"converged": int(ok.sum()), "censored": int((~ok).sum()),
+                "rounds_median": q(it, 0.5), "rounds_p90": q(it, 0.9),
+                "sweeps_median": q(tot, 0.5), "sweeps_p90": q(tot, 0.9),
+                "rounds_median_converged": q(it[ok], 0.5)}
+    itp, its = np.asarray(plain["rounds"]), np.asarray(seeded["rounds"])
+    both = (itp <= n_max) & (its <= n_max)
+    same_klo = plain["k_lo"][both] == seeded["k_lo"][both]
+    dS = []
+    for r in np.nonzero(both)[0]:
+        cover = (plain["mask"][r] > 0) & (seeded["mask"][r] > 0)
+        if cover.any():
+            dS.append(float(np.abs(plain["y"][r][cover] - seeded["y"][r][cover]).max()) * N)
+    dS = np.array(dS)
+    return {"L": L, "realizations": int(len(itp)), "sweeps_per_round": n_sweeps, "n_max": n_max,
+            "plain": arm(plain, 0.0), "seeded": arm(seeded, CANON_SWEEPS),
+            "seed_rejected": int((np.asarray(seeded["k_seed"]) < 0).sum()),
+            "fewer_rounds": int((its < itp).sum()), "more_rounds": int((its > itp).sum()),
+            "both_converged": int(both.sum()),
+            "same_lowest_level": int(same_klo.sum()),
+            "seeded_lower_level": int((seeded["k_lo"][both] < plain["k_lo"][both]).sum()),
+            "plain_lower_level": int((plain["k_lo"][both] < seeded["k_lo"][both]).sum()),
+            "max_abs_dS_median": float(np.median(dS)) if len(dS) else None,
+            "max_abs_dS_p90": float(np.quantile(dS, 0.9)) if len(dS) else None}
+
+
+def _save(path, **arrays):
+    np.savez(path, **{k: np.asarray(v) for k, v in arrays.items()})
+
+
+def _load(path):
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-L", type=int, nargs="+", default=[6, 8, 10])
@@ -250,12 +319,73 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--bench-net", action="store_true",
                     help="only time the network's training steps and BF16 inference on synthetic inputs")
+    # the workflow in stages, so that a large run can be split over several processes
+    ap.add_argument("--stage", choices=["data", "train", "eval", "report"],
+                    help="data: training data of --train-L (ids from --first-id) into --out; train: the network "
+                         "from --inputs data files into --out; eval: one arm (--arm) on --eval-real realizations "
+                         "from --eval-first into --out (the seeded arm loads the network from --inputs); report: "
+                         "the paired summary of --inputs plain and seeded arm files (no GPU)")
+    ap.add_argument("--out")
+    ap.add_argument("--inputs", nargs="*", default=[])
+    ap.add_argument("--first-id", type=int, default=0)
+    ap.add_argument("--arm", choices=["plain", "seeded"])
+    ap.add_argument("--eval-first", type=int, default=EVAL_FIRST_ID)
     args = ap.parse_args(argv)
     if args.bench_net:
         print(json.dumps(bench_net(seed=args.seed)))
         return
     t0 = time.time()
     log = lambda s: print(f"[{time.time() - t0:7.1f}s] {s}", file=sys.stderr, flush=True)
+    if args.stage == "data":
+        per_L = int(math.ceil(args.train_real / len(args.train_L)))
+        x, y, m, stats = generate(args.train_L, per_L, args.sweeps, args.f_tol, args.n_max, first_id=args.first_id,
+                                  log=log)
+        _save(args.out, x=x.cpu().numpy(), y=y.cpu().numpy(), m=m.cpu().numpy(),
+              stats=json.dumps({str(k): v for k, v in stats.items()}))
+        print(json.dumps({"stage": "data", "per_L": stats, "wall_s": time.time() - t0}))
+        return
+    if args.stage == "train":
+        import torch
+        parts = [_load(p) for p in args.inputs]
+        x = torch.tensor(np.concatenate([p["x"] for p in parts]), device="cuda")
+        y = torch.tensor(np.concatenate([p["y"] for p in parts]), device="cuda")
+        m = torch.tensor(np.concatenate([p["m"] for p in parts]), device="cuda")
+        mlp = nfm.Mlp(batch_max=256)
+        mlp.init(args.seed)
+        losses, val = train(mlp, x, y, m, epochs=args.epochs, lr=args.lr, seed=args.seed, log=log)
+        params, norm = mlp.get_params()
+        _save(args.out, params=params, norm=norm, losses=np.array(losses), val=np.float64(val if val else np.nan))
+        print(json.dumps({"stage": "train", "rows": int(x.shape[0]), "rows_with_targets": int((m.sum(1) > 0).sum()),
+                          "final_loss": losses[-1], "val_loss": val, "wall_s": time.time() - t0}))
+        mlp.close()
+        return
+    if args.stage == "eval":
+        mlp = None
+        if args.arm == "seeded":
+            net = _load(args.inputs[0])
+            mlp = nfm.Mlp(batch_max=256)
+            mlp.set_params(net["params"], net["norm"])
+        rec = run_arm(mlp, args.eval_L, args.eval_real, args.sweeps, args.f_tol, args.n_max, args.eval_first, log)
+        _save(args.out, arm=args.arm, first_id=np.int64(args.eval_first), **rec)
+        it = rec["rounds"]
+        print(json.dumps({"stage": "eval", "arm": args.arm, "realizations": args.eval_real,
+                          "converged": int((it <= args.n_max).sum()), "rounds_median": float(np.median(it)),
+                          "wall_s": time.time() - t0}))
+        return
+    if args.stage == "report":
+        arms = {"plain": [], "seeded": []}
+        for p in args.inputs:
+            d = _load(p)
+            arms[str(d.pop("arm"))].append(d)
+        # chunks of realizations in id order; the two arms must cover the same ids
+        ids = {a: [int(d["first_id"]) for d in sorted(ds, key=lambda d: int(d["first_id"]))] for a, ds in arms.items()}
+        if ids["plain"] != ids["seeded"]:
+            raise SystemExit(f"report: the arms cover different realizations: {ids}")
+        cat = lambda ds: {k: np.concatenate([d[k] for d in sorted(ds, key=lambda d: int(d["first_id"]))])
+                          for k in ds[0] if k != "first_id"}
+        print(json.dumps(paired_report(cat(arms["plain"]), cat(arms["seeded"]), args.eval_L, args.sweeps,
+                                       args.n_max)))
+        return
     per_L = int(math.ceil(args.train_real / len(args.train_L)))
     x, y, m, stats = generate(args.train_L, per_L, args.sweeps, args.f_tol, args.n_max, log=log)
     mlp = nfm.Mlp(batch_max=256)

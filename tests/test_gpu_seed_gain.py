@@ -4,8 +4,9 @@ Small scale of the learned-start workflow: targets from converged estimates of L
 realizations, the network trained on the GPU by the library's kernels, then fresh L = 6
 realizations run twice under the same seeds (the same canonical run, the same sweeps per round
 and flatness tolerance), once from the plain start and once from the seeded one. The seeded
-arm must need fewer than half the rounds on average (measured: 5 against 25), and fewer rounds
-for most realizations. The targets kernel is checked against the oracle's
+arm must need fewer than half the rounds on average (measured: 5 against 25), fewer rounds for
+most realizations and fewer sweeps in all (its canonical run included), and reach the same
+estimate: the same lowest level and S(E) within noise where both arms converged. The targets kernel is checked against the oracle's
 definition on the same estimate first.
 """
 import numpy as np
@@ -48,9 +49,18 @@ def test_seeded_start_needs_fewer_rounds(seeding):
     mlp.init(3)
     losses, val = seeding.train(mlp, x, y, m, epochs=40, lr=2e-3, seed=1)
     assert losses[-1] < 0.2 * losses[0], losses
-    it_p, it_s, ks = seeding.evaluate(mlp, 6, 128, sweeps, f_tol, n_max, first_id=2_000_000)
+    plain, seeded = seeding.evaluate(mlp, 6, 128, sweeps, f_tol, n_max, first_id=2_000_000, full=True)
+    it_p, it_s, ks = plain["rounds"], seeded["rounds"], seeded["k_seed"]
     s = seeding.summary(it_p, it_s, ks, n_max)
-    print(s)
+    rep = seeding.paired_report(plain, seeded, 6, sweeps, n_max)
+    print(s, rep)
+    # the same final estimate at equal flatness tolerance: the same lowest level found, and S(E)
+    # within the estimates' noise where both arms converged
+    assert rep["both_converged"] > 0.9 * 128, rep
+    assert rep["same_lowest_level"] > 0.9 * rep["both_converged"], rep
+    assert rep["max_abs_dS_median"] < 0.6 and rep["max_abs_dS_p90"] < 1.5, rep   # measured 0.18, 0.41
+    # fewer sweeps in all, the seeded arm paying for its canonical run
+    assert rep["seeded"]["sweeps_median"] < rep["plain"]["sweeps_median"], rep
     assert s["seed_rejected"] < 13, s
     assert s["seeded"]["censored"] == 0, s
     assert s["seeded"]["mean"] < 0.5 * s["plain"]["mean"], s     # measured: about 5 rounds against 25
