@@ -100,8 +100,9 @@ def setup(nfm, mix, W, profile):
 
 def counter_summary(config, kernel, sweeps_per_launch, key):
     """A figure from a committed rocprofv3 counter summary under profiles/ (lines 'key: value')
-    for this workload, kernel form and launch size, or None when there is none or the kernel's
-    sources changed since the counters were taken."""
+    for this workload, kernel form and launch size (sweeps_per_launch None: any launch size, for
+    per-attempt figures), or None when there is none or the kernel's sources changed since the
+    counters were taken."""
     digest = kernel_source_digest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         kv = {}
@@ -114,7 +115,8 @@ def counter_summary(config, kernel, sweeps_per_launch, key):
         except OSError:
             continue
         if (key in kv and kv.get("config") == config and kv.get("kernel") == kernel
-                and kv.get("source_sha256") == digest and kv.get("sweeps_per_launch") == str(sweeps_per_launch)):
+                and kv.get("source_sha256") == digest
+                and (sweeps_per_launch is None or kv.get("sweeps_per_launch") == str(sweeps_per_launch))):
             try:
                 return float(kv[key])
             except ValueError:
@@ -330,7 +332,8 @@ def main():
     kernel = b.last_kernel()   # the form the library chose for the timed launches
     spl = tn["sweeps_per_launch"]
     traffic = counter_summary(args.config, kernel, spl, "traffic_bytes_per_launch") if S % spl == 0 else None
-    valu = counter_summary(args.config, kernel, spl, "valu_lane_instructions_per_attempt")
+    # instructions per attempt do not depend on the launch size (counters of one launch size serve)
+    valu = counter_summary(args.config, kernel, None, "valu_lane_instructions_per_attempt")
 
     line = {
         "metric": "spin-flip attempts/s per GPU",

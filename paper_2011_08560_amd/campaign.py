@@ -98,23 +98,25 @@ def adapt_temperatures(b, M, rounds=40, sweeps=500, band=(0.4, 0.6), log=None):
     return it, rates
 
 
-def tempering(b, L, min_trips, chunk, cap, burn=1000, adaptive=False, log=None):
+def tempering(b, L, min_trips, chunk, cap, burn=1000, adaptive=False, log=None, adapt_M=None, adapt_T=None,
+              adapt_rounds=40, adapt_sweeps=500):
     """Round-trip times of parallel tempering (in PT sweeps) between each realization's lowest
     energy found by the weight iteration and the mean energy of the hottest slot (averaged over
     the batch after a burn-in). adaptive: the paper's protocol (M from PAPER_M, temperatures in
-    ADAPT_T adapted per realization) instead of the fixed 32-temperature ladder."""
+    ADAPT_T adapted per realization; adapt_M / adapt_T override them) instead of the fixed
+    32-temperature ladder."""
     info = b.rec_read_info()
     b.compute_energies()
     extra = {}
     if adaptive:
-        M = PAPER_M.get(L, 20)
-        t0, t1 = ADAPT_T
+        M = adapt_M or PAPER_M.get(L, 20)
+        t0, t1 = adapt_T or ADAPT_T
         b.pt_init([t0 * (t1 / t0) ** (s / (M - 1)) for s in range(M)])
-        rounds, rates = adapt_temperatures(b, M, log=log)
+        rounds, rates = adapt_temperatures(b, M, rounds=adapt_rounds, sweeps=adapt_sweeps, log=log)
         rates = np.asarray(rates).reshape(b.n_real, M - 1)
         in_band = ((rates >= 0.4) & (rates <= 0.6)).all(axis=1)
         q = np.quantile(rates, [0.05, 0.5, 0.95])
-        extra = {"M": M, "adapt_rounds": rounds, "rates_min": float(rates.min()), "rates_max": float(rates.max()),
+        extra = {"M": M, "T_range": [t0, t1], "adapt_rounds": rounds, "rates_min": float(rates.min()), "rates_max": float(rates.max()),
                  "rates_mean": float(rates.mean()), "rates_q05_q50_q95": [float(x) for x in q],
                  "realizations_in_band": int(in_band.sum())}
         if log:
@@ -175,7 +177,8 @@ def analyse(taus: dict, ref="pl", eps=1e-4, blocks=0):
 
 
 def compare(L, n_real, methods=METHODS, min_trips=100, iter_sweeps=None, f_tol=0.5, n_max=60, chunk=None,
-            cap=None, first_id=0, eps=1e-4, blocks=0, log=None):
+            cap=None, first_id=0, eps=1e-4, blocks=0, log=None, adapt_M=None, adapt_T=None, adapt_rounds=40,
+            adapt_sweeps=500):
     """The comparison of Secs. III-V at one L (round trips of every method, their distributions
     and Table I's ratios); returns a JSON-able record."""
     iter_sweeps = iter_sweeps or 1000 * L * L
@@ -194,7 +197,8 @@ def compare(L, n_real, methods=METHODS, min_trips=100, iter_sweeps=None, f_tol=0
     for m in ("pt", "pt_adaptive"):
         if m in methods:
             taus[m], cost[m], e_top, extra = tempering(b, L, min_trips, chunk, cap, adaptive=(m == "pt_adaptive"),
-                                                       log=log)
+                                                       log=log, adapt_M=adapt_M, adapt_T=adapt_T,
+                                                       adapt_rounds=adapt_rounds, adapt_sweeps=adapt_sweeps)
             rec[m] = {"e_top": e_top, **extra}
             if m == "pt":
                 rec[m]["temperatures"] = [PT_TEMPS[0], PT_TEMPS[-1], len(PT_TEMPS)]
@@ -349,6 +353,11 @@ def main(argv=None):
                     help="with --estimators: also the recursion seeded by a network trained on these sizes")
     ap.add_argument("--seed-train-real", type=int, default=2048)
     ap.add_argument("--save-tau", help="comparison: write every method's per-realization times to this .npz")
+    ap.add_argument("--adapt-M", type=int, default=0, help="pt_adaptive: replicas (default: the paper's M for L)")
+    ap.add_argument("--adapt-T", type=float, nargs=2, metavar=("TMIN", "TMAX"),
+                    help="pt_adaptive: temperature range (default [0.2, 3.2])")
+    ap.add_argument("--adapt-rounds", type=int, default=40)
+    ap.add_argument("--adapt-sweeps", type=int, default=500)
     ap.add_argument("--analyse", nargs="+", metavar="NPZ",
                     help="no simulation: pool the methods of earlier --save-tau files (same L, realizations "
                          "and seeds; a later file's method replaces an earlier one's) and analyse them")
@@ -405,7 +414,9 @@ def main(argv=None):
                        args.f_tol, args.n_max, args.chunk or None, args.cap or None, args.first_id, log)
         else:
             rec = compare(L, args.real, args.methods, args.min_trips, args.iter_sweeps or None, args.f_tol,
-                          args.n_max, args.chunk or None, args.cap or None, args.first_id, args.eps, args.blocks, log)
+                          args.n_max, args.chunk or None, args.cap or None, args.first_id, args.eps, args.blocks, log,
+                          adapt_M=args.adapt_M or None, adapt_T=tuple(args.adapt_T) if args.adapt_T else None,
+                          adapt_rounds=args.adapt_rounds, adapt_sweeps=args.adapt_sweeps)
             tau = rec.pop("tau")
             if args.save_tau:
                 np.savez(args.save_tau, **{f"tau_{m}": np.array([np.nan if x is None else x for x in t], float)

@@ -48,6 +48,7 @@ def test_counter_summary_matches_workload_kernel_and_source(tmp_path, monkeypatc
     assert bench.counter_summary("c4", "k_sweeps_queue", 256, "traffic_bytes_per_launch") is None
     assert bench.counter_summary("c3", "k_sweeps_queue", 1024, "traffic_bytes_per_launch") is None
     assert bench.counter_summary("c4", "k_sweeps_queue", 1024, "valu_lane_instructions_per_attempt") is None
+    assert bench.counter_summary("c4", "k_sweeps_queue", None, "traffic_bytes_per_launch") == 123.5
     (tmp_path / "profiles" / "k_x_traffic.txt").write_text(
         "kernel: k_sweeps_queue\nconfig: c4\nsweeps_per_launch: 1024\ntraffic_bytes_per_launch: 1\n"
         "source_sha256: 00\n")
