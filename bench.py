@@ -285,7 +285,9 @@ def main():
     stream = torch.cuda.current_stream()
     attempts_per_step = (PT_M * (64 // PT_M) * (W // 64) if pt else W) * S * sum(l ** 3 for l in Ls)
     tn = b.get_tuning()
-    groups = 1 if len(mix) == 1 or (not pt and tn["schedule"] == 1) else len(mix)
+    # launches per step: per-size launches run one per size; the persistent forms one per chunk
+    # (the split form's two concurrent queues count as one launch: they share one fork and join)
+    groups = 1 if len(mix) == 1 or (not pt and tn["schedule"] in (1, 2)) else len(mix)
     launches_per_step = math.ceil(S / tn["sweeps_per_launch"]) * groups
 
     def step():

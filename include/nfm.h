@@ -297,7 +297,13 @@ nfm_status nfm_wl_to_rec(nfm_ctx* ctx, int32_t profile, double pl_dE, double pl_
  *     walkers' histogram counts on chip and adds them to the histograms when it ends.
  *   schedule: 0 = one launch per lattice size of the batch; 1 = one persistent launch for the
  *     whole batch, whose workgroups take waves of walkers from a queue ordered by decreasing N
- *     (longest first), so that realizations of uneven size share the GPU.
+ *     (longest first), so that realizations of uneven size share the GPU; 2 = split: the
+ *     largest size's waves as a persistent queue of their own in a kernel form whose waves each
+ *     hold a whole SIMD (their serial chains bound a sweep of the batch, and run fastest alone),
+ *     beside a persistent queue over the remaining sizes on the SIMDs left free (at most half the
+ *     SIMDs go to the largest size), launched on a second stream of the library's behind a short
+ *     wait, forked from and joined to the context's stream; a batch of one size runs as 1. A
+ *     persistent launch over sizes up to 8 or 10 uses the form compiled for them (fewer registers).
  *   waves_per_cu: persistent schedule only, resident workgroups per compute unit (0 = as many
  *     as fit).
  *   hist: extent of a launch's on-chip histogram. 0 automatic: every level of the realization
@@ -323,7 +329,7 @@ nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
 /* Autotuner for mixed batches (no passage of the paper: a launch-configuration search). Times
  * every candidate tuning (speculation off/on x sweeps per launch {16, 64, 256, 1024} x {per-size
  * launches without and (no speculation) with the generator wave, persistent queue with as many
- * workgroups as fit, 4 or 8 per CU}) for calib_sweeps
+ * workgroups as fit, 4 or 8 per CU, split}) for calib_sweeps
  * sweeps on the batch itself, then restores spins, walker state and histograms, so the
  * calibration leaves no trace in the results (the sweep counter does not move). The fastest
  * candidate (spin-flip attempts per second) is applied and returned in *best. Results are cached

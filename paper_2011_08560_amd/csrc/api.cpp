@@ -143,6 +143,10 @@ struct nfm_ctx {
   // waves grouped by L
   std::vector<int> group_L;
   std::vector<int64_t> group_first_wave, group_n_waves;
+  // split persistent launch (schedule 2): the second stream, and the fork / join events between
+  // it and the context's stream
+  hipStream_t split_stream = nullptr;
+  hipEvent_t split_fork = nullptr, split_join = nullptr;
   std::string err;
 
   RealInfo* d_reals() { return (RealInfo*)(ws + lay.reals); }
@@ -379,9 +383,23 @@ nfm_status nfm_create(nfm_ctx** out, const nfm_batch_desc* desc, void* dev_works
   return NFM_OK;
 }
 
+static void drop_split_stream(nfm_ctx* c) {
+  if (c->split_stream) {
+    (void)hipStreamSynchronize(c->split_stream);
+    (void)hipStreamDestroy(c->split_stream);
+  }
+  if (c->split_fork) (void)hipEventDestroy(c->split_fork);
+  if (c->split_join) (void)hipEventDestroy(c->split_join);
+  c->split_stream = nullptr;
+  c->split_fork = c->split_join = nullptr;
+}
+
 void nfm_destroy(nfm_ctx* ctx) {
   if (!ctx) return;
-  if (hipSetDevice(ctx->device) == hipSuccess) (void)hipStreamSynchronize(ctx->stream);
+  if (hipSetDevice(ctx->device) == hipSuccess) {
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_split_stream(ctx);
+  }
   delete ctx;
 }
 
@@ -583,6 +601,48 @@ static nfm::SweepArgs muca_args(nfm_ctx* c, uint64_t t0, uint32_t n, int trace_c
   return a;
 }
 
+// The split persistent launch (schedule 2). A sweep of the whole batch is bound by the serial
+// chains of its largest lattices (one attempt after another per walker, Sec. II). Their waves run
+// as a persistent queue of their own in the SIMD-exclusive kernel form, each alone on a SIMD and so
+// at the chain's own issue rate, beside a second persistent queue over the remaining sizes (in the
+// form compiled for them) on the SIMDs left free. The second queue is launched on its own stream
+// behind a short wait, so that the first one is placed first.
+struct SplitPart {
+  int64_t first = 0, n = 0;   // slice of the work-queue order
+  int maxl = 0, lds_rows = 1, K = 1;
+};
+
+static bool plan_split(const nfm_ctx* c, SplitPart* big, SplitPart* rest) {
+  const int G = (int)c->group_L.size();   // sizes ascending; the order lists waves longest first
+  if (G < 2) return false;
+  *big = SplitPart{};
+  *rest = SplitPart{};
+  big->n = c->group_n_waves[G - 1];
+  big->maxl = c->group_L[G - 1];
+  rest->first = big->n;
+  rest->n = c->lay.total_waves - big->n;
+  rest->maxl = c->group_L[G - 2];
+  for (const auto& ri : c->reals) {
+    SplitPart* p = ri.L == big->maxl ? big : rest;
+    p->lds_rows = std::max(p->lds_rows, ri.rows);
+    p->K = std::max(p->K, ri.K);
+  }
+  return rest->n > 0;
+}
+
+static bool ensure_split_stream(nfm_ctx* c) {
+  if (c->split_stream) return true;
+  if (hipStreamCreateWithFlags(&c->split_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->split_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->split_join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    c->err = "split launch unavailable: stream or event creation failed";
+    drop_split_stream(c);
+    return false;
+  }
+  return true;
+}
+
 // Launch n multicanonical sweeps starting at sweep t0 under the given tuning (no checks).
 static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int speculate, uint32_t per_launch,
                                 int schedule, int waves_per_cu, int hist_mode, int ws_mode, int trace_cap) {
@@ -591,18 +651,44 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
     lds_all = std::max(lds_all, ri.rows);
     k_all = std::max(k_all, ri.K);
   }
+  // schedule 2 splits off the largest size (a batch of one size runs as the plain persistent queue)
+  SplitPart big, rest;
+  const bool split = schedule == 2 && plan_split(c, &big, &rest) && ensure_split_stream(c);
   uint64_t done = 0;
   while (done < n_sweeps) {
     const uint32_t chunk = (uint32_t)std::min<uint64_t>(per_launch, n_sweeps - done);
     nfm::SweepArgs a = muca_args(c, t0 + done, chunk, trace_cap);
-    if (schedule == 1) {
+    if (split) {
       const bool spec = speculate == 1;
-      int wpc = waves_per_cu;
-      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all, k_all, hist_mode));
+      const int32_t* order = (const int32_t*)(c->ws + c->lay.order);
+      uint32_t* counter = (uint32_t*)(c->ws + c->lay.counter);
+      // at most half the SIMDs go to the largest lattices; the rest of the queue over the SIMDs left
+      const int64_t simds = 4LL * c->n_cu;
+      const int64_t grid_big = std::max<int64_t>(1, std::min<int64_t>(big.n, simds / 2));
+      const int per_simd = std::max(1, nfm::queue_blocks_per_cu(spec, rest.lds_rows, rest.K, hist_mode, rest.maxl) / 4);
+      const int64_t grid_rest = std::max<int64_t>(1, std::min<int64_t>(rest.n, per_simd * (simds - grid_big)));
+      NFM_HIP(c, hipEventRecord(c->split_fork, c->stream));
+      hipError_t e = nfm::launch_muca_queue(a, order, (int)big.n, counter, (int)grid_big, c->n_cu, big.lds_rows, big.K,
+                                            hist_mode, spec, c->stream, big.maxl, true);
+      if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_queue (largest): ") + hipGetErrorString(e));
+      NFM_HIP(c, hipStreamWaitEvent(c->split_stream, c->split_fork, 0));
+      e = nfm::launch_hold(c->split_stream);
+      if (e == hipSuccess)
+        e = nfm::launch_muca_queue(a, order + rest.first, (int)rest.n, counter + 16, (int)grid_rest, c->n_cu,
+                                   rest.lds_rows, rest.K, hist_mode, spec, c->split_stream, rest.maxl, false);
+      if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_queue (rest): ") + hipGetErrorString(e));
+      NFM_HIP(c, hipEventRecord(c->split_join, c->split_stream));
+      NFM_HIP(c, hipStreamWaitEvent(c->stream, c->split_join, 0));
+      nfm::note_partitioned_launch(spec);
+    } else if (schedule >= 1) {
+      const bool spec = speculate == 1;
+      const int maxl = c->group_L.empty() ? nfm::kMaxL : c->group_L.back();
+      int wpc = schedule == 1 ? waves_per_cu : 0;
+      if (wpc <= 0) wpc = std::max(1, nfm::queue_blocks_per_cu(spec, lds_all, k_all, hist_mode, maxl));
       const int64_t grid = std::min<int64_t>(c->lay.total_waves, (int64_t)wpc * c->n_cu);
       hipError_t e = nfm::launch_muca_queue(a, (const int32_t*)(c->ws + c->lay.order), (int)c->lay.total_waves,
                                             (uint32_t*)(c->ws + c->lay.counter), (int)grid, c->n_cu, lds_all, k_all,
-                                            hist_mode, spec, c->stream);
+                                            hist_mode, spec, c->stream, maxl);
       if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("muca_queue: ") + hipGetErrorString(e));
     } else {
       for (size_t g = 0; g < c->group_L.size(); ++g) {
@@ -1049,10 +1135,10 @@ nfm_status nfm_rec_set_state(nfm_ctx* c, int32_t r, const double* b, const doubl
 nfm_status nfm_set_tuning(nfm_ctx* c, const nfm_tuning* t) {
   if (!c || !t) return NFM_EINVAL;
   if (t->speculate < -1 || t->speculate > 1 || t->sweeps_per_launch < 0 || t->sweeps_per_launch > (1 << 20) ||
-      t->schedule < 0 || t->schedule > 1 ||
+      t->schedule < 0 || t->schedule > 2 ||
       t->waves_per_cu < 0 || t->waves_per_cu > 64 || t->hist < 0 || t->hist > 3 || t->ws < 0 || t->ws > 2)
     return fail(c, NFM_EINVAL,
-                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch in [0, 2^20], schedule in {0,1}, waves_per_cu in "
+                "set_tuning: speculate in {-1,0,1}, sweeps_per_launch in [0, 2^20], schedule in {0,1,2}, waves_per_cu in "
                 "[0,64], hist in {0,1,2,3}, ws in {0,1,2}");
   c->speculate = t->speculate;
   c->sweeps_per_launch = t->sweeps_per_launch == 0 ? kMaxSweepsPerLaunch : (uint32_t)t->sweeps_per_launch;
@@ -1148,6 +1234,8 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
         cand.push_back(nfm_tuning{spec, ch, 1, 0, 0, 0});
         for (int wpc : {4, 8})
           if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc, 0, 0});
+        SplitPart big, rest;
+        if (plan_split(c, &big, &rest)) cand.push_back(nfm_tuning{spec, ch, 2, 0, 0, 0});
       }
     hipEvent_t e0, e1;
     NFM_HIP(c, hipEventCreate(&e0));

@@ -75,16 +75,24 @@ hipError_t launch_features(const RealInfo* reals, int n_real, const uint32_t* ja
 // 3 the table rows alone)
 hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_rows, int hist_levels, int n_cu,
                               int hist_mode, int ws_mode, bool spec, hipStream_t s);
-// persistent launch over all waves of the batch; order = wave indices, longest first
+// persistent launch over n_items waves; order = wave indices, longest first; maxl = the largest L
+// among them (at most 8 or 10: the kernel forms for smaller lattices, which hold fewer registers);
+// solo: the form whose waves each hold a whole SIMD
 hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uint32_t* counter, int grid, int n_cu,
-                             int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s);
+                             int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s, int maxl,
+                             bool solo = false);
 // resident workgroups per CU of the persistent kernel (0 on error)
-int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode);
+int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode, int maxl, bool solo = false);
+// a short bounded wait on stream s (orders the placement of two launches on two streams)
+hipError_t launch_hold(hipStream_t s);
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s);
 // the exchange thresholds of realization r as the sweep kernel computes them (inspection)
 hipError_t launch_pt_swap_table(const double* q, int r, int M, int D, uint32_t* swap, hipStream_t s);
 // name of the sweep kernel the last launch on this host thread used
 const char* last_sweep_kernel();
+// record a split persistent launch (the largest lattices in the SIMD-exclusive form beside the
+// others) as the last launch
+void note_partitioned_launch(bool spec);
 bool sweep_supported(int L);
 
 }  // namespace nfm

@@ -866,11 +866,17 @@ __global__ void __launch_bounds__(64) k_sweeps(SweepArgs A) {
 // work items (one wave of walkers for this launch's sweeps) from a global counter until the
 // queue is empty. The queue lists waves longest-first (by N), so the last items to start are
 // the cheapest ones. Results do not depend on which workgroup runs which item.
-template <bool SPEC>
+// MAXL: the largest lattice the launch's items have (a launch over small lattices only holds
+// fewer registers per wave, so more waves stay resident). SOLO: the wave claims the whole
+// register file of its SIMD (all 256 accumulation registers besides its own), so no other wave
+// shares that SIMD's issue slots while it runs; for the largest lattices, whose serial chains
+// bound the batch.
+template <bool SPEC, int MAXL, bool SOLO = false>
 __global__ void __launch_bounds__(64) k_sweeps_queue(SweepArgs A, const int32_t* __restrict__ order, int n_items,
                                                      uint32_t* __restrict__ counter) {
   extern __shared__ uint32_t stab[];
   (void)stab;
+  if constexpr (SOLO) asm volatile("" ::: "a255");
   for (;;) {
     __syncthreads();  // the previous item's table reads are done before the next table is loaded
     int item = 0;
@@ -880,11 +886,11 @@ __global__ void __launch_bounds__(64) k_sweeps_queue(SweepArgs A, const int32_t*
     const int wave = order[item];
     switch (A.reals[A.wave_real[wave]].L) {
       case 2: sweep_wave<2, SPEC, false>(A, wave); break;
-      case 4: sweep_wave<4, SPEC, false>(A, wave); break;
-      case 6: sweep_wave<6, SPEC, false>(A, wave); break;
-      case 8: sweep_wave<8, SPEC, false>(A, wave); break;
-      case 10: sweep_wave<10, SPEC, false>(A, wave); break;
-      case 12: sweep_wave<12, SPEC, false>(A, wave); break;
+      case 4: if constexpr (MAXL >= 4) sweep_wave<4, SPEC, false>(A, wave); break;
+      case 6: if constexpr (MAXL >= 6) sweep_wave<6, SPEC, false>(A, wave); break;
+      case 8: if constexpr (MAXL >= 8) sweep_wave<8, SPEC, false>(A, wave); break;
+      case 10: if constexpr (MAXL >= 10) sweep_wave<10, SPEC, false>(A, wave); break;
+      case 12: if constexpr (MAXL >= 12) sweep_wave<12, SPEC, false>(A, wave); break;
       default: break;
     }
   }
@@ -912,6 +918,9 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 // Name of the sweep kernel the last launch on this host thread used (for reports).
 static thread_local char g_last_kernel[48] = "none";
 const char* last_sweep_kernel() { return g_last_kernel; }
+void note_partitioned_launch(bool spec) {
+  snprintf(g_last_kernel, sizeof(g_last_kernel), "%s_solo", spec ? "k_sweeps_queue_spec" : "k_sweeps_queue");
+}
 static void note_kernel(const char* form, int L) { snprintf(g_last_kernel, sizeof(g_last_kernel), "%s<%d>", form, L); }
 
 template <int L, bool SPEC, bool PT, bool XT = false>
@@ -1035,13 +1044,30 @@ hipError_t launch_muca_sweeps(int L, const SweepArgs& a, int n_waves, int lds_ro
   return launch_any(L, a, n_waves, lds_rows, hist_levels, n_cu, hist_mode, ws_mode, spec, false, s);
 }
 
+// The compiled queue forms: MAXL 8, 10 or 12, and the SIMD-exclusive form (MAXL 12).
+static int queue_maxl(int maxl) { return maxl <= 8 ? 8 : maxl <= 10 ? 10 : kMaxL; }
+
 template <bool SPEC>
+static const void* queue_kernel_S(int maxl, bool solo) {
+  if (solo) return reinterpret_cast<const void*>(&k_sweeps_queue<SPEC, kMaxL, true>);
+  switch (queue_maxl(maxl)) {
+    case 8: return reinterpret_cast<const void*>(&k_sweeps_queue<SPEC, 8>);
+    case 10: return reinterpret_cast<const void*>(&k_sweeps_queue<SPEC, 10>);
+    default: return reinterpret_cast<const void*>(&k_sweeps_queue<SPEC, kMaxL>);
+  }
+}
+
+static const void* queue_kernel(bool spec, int maxl, bool solo) {
+  return spec ? queue_kernel_S<true>(maxl, solo) : queue_kernel_S<false>(maxl, solo);
+}
+
+template <bool SPEC, int MAXL, bool SOLO>
 static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n_items, uint32_t* counter, int grid,
                                  size_t lds_bytes, hipStream_t s) {
   static int checked = 0;
   if (!checked) {
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps_queue<SPEC>));
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_sweeps_queue<SPEC, MAXL, SOLO>));
     if (e != hipSuccess) return e;
     if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     checked = 1;
@@ -1050,35 +1076,60 @@ static hipError_t launch_queue_S(const SweepArgs& a, const int32_t* order, int n
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   snprintf(g_last_kernel, sizeof(g_last_kernel), "%s", SPEC ? "k_sweeps_queue_spec" : "k_sweeps_queue");
-  hipLaunchKernelGGL((k_sweeps_queue<SPEC>), dim3(grid), dim3(64), lds_bytes, s, a, order, n_items, counter);
+  hipLaunchKernelGGL((k_sweeps_queue<SPEC, MAXL, SOLO>), dim3(grid), dim3(64), lds_bytes, s, a, order, n_items,
+                     counter);
   return hipGetLastError();
 }
 
-// LDS of the persistent kernel: the largest table, the couplings of the largest lattice and the
-// histogram planned for the largest table and level count of the batch.
-static HistPlan queue_plan(bool spec, int lds_rows, int hist_levels, int want_blocks, int mode) {
-  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
-                       : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
-  return plan_hist(f, (size_t)lds_rows * 32 + (size_t)jk_words(kMaxL) * 4, lds_rows, hist_levels, want_blocks, mode);
+template <bool SPEC>
+static hipError_t launch_queue_M(int maxl, bool solo, const SweepArgs& a, const int32_t* order, int n_items,
+                                 uint32_t* counter, int grid, size_t lds_bytes, hipStream_t s) {
+  if (solo) return launch_queue_S<SPEC, kMaxL, true>(a, order, n_items, counter, grid, lds_bytes, s);
+  switch (queue_maxl(maxl)) {
+    case 8: return launch_queue_S<SPEC, 8, false>(a, order, n_items, counter, grid, lds_bytes, s);
+    case 10: return launch_queue_S<SPEC, 10, false>(a, order, n_items, counter, grid, lds_bytes, s);
+    default: return launch_queue_S<SPEC, kMaxL, false>(a, order, n_items, counter, grid, lds_bytes, s);
+  }
 }
 
-int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode) {
+// LDS of the persistent kernel: the largest table, the couplings of the largest lattice and the
+// histogram planned for the largest table and level count of the launch's items.
+static HistPlan queue_plan(bool spec, int maxl, bool solo, int lds_rows, int hist_levels, int want_blocks,
+                           int mode) {
+  const int jl = solo ? kMaxL : queue_maxl(maxl);
+  return plan_hist(queue_kernel(spec, maxl, solo), (size_t)lds_rows * 32 + (size_t)jk_words(jl) * 4, lds_rows,
+                   hist_levels, want_blocks, mode);
+}
+
+int queue_blocks_per_cu(bool spec, int lds_rows, int hist_levels, int hist_mode, int maxl, bool solo) {
   int n = 0;
-  const void* f = spec ? reinterpret_cast<const void*>(&k_sweeps_queue<true>)
-                       : reinterpret_cast<const void*>(&k_sweeps_queue<false>);
-  const HistPlan h = queue_plan(spec, lds_rows, hist_levels, 1 << 20, hist_mode);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64, h.lds) != hipSuccess) return 0;
+  const void* k = queue_kernel(spec, maxl, solo);
+  const HistPlan h = queue_plan(spec, maxl, solo, lds_rows, hist_levels, 1 << 20, hist_mode);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64, h.lds) != hipSuccess) return 0;
   return n;
 }
 
 hipError_t launch_muca_queue(SweepArgs a, const int32_t* order, int n_items, uint32_t* counter, int grid, int n_cu,
-                             int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s) {
-  if (grid < 1 || n_items < 0) return hipErrorInvalidValue;
-  const HistPlan h = queue_plan(spec, lds_rows, hist_levels, (grid + n_cu - 1) / std::max(n_cu, 1), hist_mode);
+                             int lds_rows, int hist_levels, int hist_mode, bool spec, hipStream_t s, int maxl,
+                             bool solo) {
+  if (grid < 1 || n_items < 0 || maxl < 2 || maxl > kMaxL) return hipErrorInvalidValue;
+  const HistPlan h =
+      queue_plan(spec, maxl, solo, lds_rows, hist_levels, (grid + n_cu - 1) / std::max(n_cu, 1), hist_mode);
   a.hist_margin = h.margin;
   a.hist_n = h.n;
-  return spec ? launch_queue_S<true>(a, order, n_items, counter, grid, h.lds, s)
-              : launch_queue_S<false>(a, order, n_items, counter, grid, h.lds, s);
+  return spec ? launch_queue_M<true>(maxl, solo, a, order, n_items, counter, grid, h.lds, s)
+              : launch_queue_M<false>(maxl, solo, a, order, n_items, counter, grid, h.lds, s);
+}
+
+// A short bounded wait (six sleeps of about 8k cycles each) on one stream, so that a launch
+// queued on another stream at the same moment is placed on the CUs first.
+__global__ void k_hold() {
+  for (int i = 0; i < 6; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
+hipError_t launch_hold(hipStream_t s) {
+  hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_pt_sweeps(int L, const SweepArgs& a, int n_waves, hipStream_t s) {

@@ -79,7 +79,11 @@ CONFIGS = [dict(schedule=1, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hi
            dict(schedule=0, speculate=1, sweeps_per_launch=9, waves_per_cu=0, hist=3, ws=0),
            dict(schedule=0, speculate=0, sweeps_per_launch=11, waves_per_cu=0, hist=1, ws=0),
            dict(schedule=0, speculate=0, sweeps_per_launch=13, waves_per_cu=0, hist=0, ws=2),
-           dict(schedule=0, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0, ws=1)]
+           dict(schedule=0, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0, ws=1),
+           # split: the largest size in the SIMD-exclusive form beside a queue over the others
+           dict(schedule=2, speculate=0, sweeps_per_launch=0, waves_per_cu=0, hist=0, ws=0),
+           dict(schedule=2, speculate=1, sweeps_per_launch=7, waves_per_cu=0, hist=1, ws=0),
+           dict(schedule=2, speculate=0, sweeps_per_launch=16, waves_per_cu=0, hist=3, ws=0)]
 
 
 def test_schedules_give_identical_results(nfm, orc):
@@ -90,21 +94,25 @@ def test_schedules_give_identical_results(nfm, orc):
     want = _state(ref)
     ref.close()
     for cfg in CONFIGS:
+        print("tuning", cfg, flush=True)
         b = _batch(nfm, orc, MIX, n)
         b.set_tuning(**cfg)
         assert b.get_tuning() == dict(cfg, sweeps_per_launch=cfg["sweeps_per_launch"] or 1024)
         b.run_sweeps(n // 3)
         b.run_sweeps(n - n // 3)
+        if cfg["schedule"] == 2:
+            assert b.last_kernel().endswith("_solo"), (b.last_kernel(), b._lib.nfm_last_error(b.ctx))
         _same(_state(b), want)
         b.close()
 
 
-@pytest.mark.parametrize("hist", [0, 3])
-def test_queue_matches_oracle(nfm, orc, hist):
+@pytest.mark.parametrize("schedule,hist", [(1, 0), (1, 3), (2, 0)])
+def test_queue_matches_oracle(nfm, orc, schedule, hist):
     n, first = 24, 5
     b = _batch(nfm, orc, MIX, 0, first=first)
-    b.set_tuning(schedule=1, speculate=1, sweeps_per_launch=10, hist=hist)
+    b.set_tuning(schedule=schedule, speculate=1, sweeps_per_launch=10, hist=hist)
     b.run_sweeps(n)
+    assert b.last_kernel() == ("k_sweeps_queue_spec" if schedule == 1 else "k_sweeps_queue_spec_solo")
     ws = b.read_walkers()
     H = b.read_histograms()
     tabs = _tables(orc, MIX, first)
@@ -150,3 +158,21 @@ def test_autotune_restores_state_and_caches(nfm, orc, tmp_path):
     _same(_state(c), after)
     b.close()
     c.close()
+
+
+def test_small_lattice_queue_and_split_fallback(nfm, orc):
+    """Batches of sizes up to 8 and up to 10 run the queue forms compiled for them; schedule 2 on a
+    batch of one size falls back to the plain queue; all bit for bit as the per-size launches."""
+    n = 30
+    for Ls in ([4, 8, 6, 8, 4, 2], [8, 8, 8], [10, 4, 8, 10, 6]):
+        ref = _batch(nfm, orc, Ls, n)
+        ref.set_tuning(schedule=0)
+        ref.run_sweeps(n)
+        want = _state(ref)
+        ref.close()
+        for sch in (1, 2):
+            b = _batch(nfm, orc, Ls, n)
+            b.set_tuning(schedule=sch, sweeps_per_launch=8)
+            b.run_sweeps(n)
+            _same(_state(b), want)
+            b.close()

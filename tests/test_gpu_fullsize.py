@@ -177,8 +177,9 @@ def test_recursion_full_size(nfm, orc, bench, config, form, n_sample):
 
 
 def test_mixed_queue_full_size(nfm, orc, bench):
-    """The mixed batch under the persistent queue (launches of 256 sweeps, with and without
-    speculation, both forms the autotuner picks for it), two realizations of every size."""
+    """The mixed batch under the persistent queue and the split launch (launches of 256
+    sweeps, with and without speculation: the forms the autotuner picks from), two realizations
+    of every size against the oracle; all forms agree on the whole batch bit for bit."""
     mix, W, _, _ = bench.CONFIGS["c4"]
     profile = bench.PROFILES["c4"]
     Ls = [L for L, R in mix for _ in range(R)]
@@ -188,10 +189,10 @@ def test_mixed_queue_full_size(nfm, orc, bench):
         start += R
     refs = None
     results = []
-    for spec in (0, 1):
-        print("full size: c4 queue, speculate", spec, flush=True)
+    for schedule, spec in ((1, 0), (1, 1), (2, 0), (2, 1)):
+        print("full size: c4, schedule", schedule, "speculate", spec, flush=True)
         b, _ = bench.setup(nfm, mix, W, profile)
-        b.set_tuning(speculate=spec, sweeps_per_launch=256, schedule=1)
+        b.set_tuning(speculate=spec, sweeps_per_launch=256, schedule=schedule)
         if refs is None:
             refs = _refs(orc, bench, Ls, ids, W)
             tabs = _sync_tables(b, orc, refs, profile)
@@ -202,18 +203,20 @@ def test_mixed_queue_full_size(nfm, orc, bench):
                 if not np.array_equal(dthr, thr):
                     b.set_thresholds(r, thr, row0)
         b.run_sweeps(512)
-        assert b.last_kernel() == ("k_sweeps_queue_spec" if spec else "k_sweeps_queue")
+        form = ("k_sweeps_queue_spec" if spec else "k_sweeps_queue") + ("_solo" if schedule == 2 else "")
+        assert b.last_kernel() == form
         if not results:
             _compare_round(b, orc, refs, ref_tabs, 512, W)
         ws = b.read_walkers()
         results.append((ws, b.read_histograms(), b.get_spins(0, b.n_walkers)))
         b.close()
-    # the two forms agree on the whole batch, bit for bit
-    (w0, h0, s0), (w1, h1, s1) = results
-    for f in FIELDS:
-        assert np.array_equal(w0[f], w1[f]), f
-    assert np.array_equal(h0, h1)
-    assert np.array_equal(s0, s1)
+    # every form agrees on the whole batch, bit for bit
+    (w0, h0, s0) = results[0]
+    for (w1, h1, s1) in results[1:]:
+        for f in FIELDS:
+            assert np.array_equal(w0[f], w1[f]), f
+        assert np.array_equal(h0, h1)
+        assert np.array_equal(s0, s1)
 
 
 def test_tempering_full_size(nfm, orc, bench):
