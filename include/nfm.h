@@ -211,6 +211,16 @@ nfm_status nfm_set_histograms(nfm_ctx* ctx, const uint64_t* host_src);
 /* Clear every walker's round-trip state, counters and new_min (E and E_min kept), e.g. before
  * a production run (Sec. III: round trips are counted in production). */
 nfm_status nfm_reset_round_trips(nfm_ctx* ctx);
+/* Stuck-walker watch (failure detection; no passage of the paper defines it: Sec. III counts
+ * round trips between the energy bounds, and a walker that stops completing them holds up its
+ * sample's requeue for 100 trips). Flags every walker whose last completed round trip lies
+ * window_sweeps or more sweeps before the context's sweep counter; a walker without one counts
+ * from the sweep at which its round-trip state was last cleared (nfm_compute_energies,
+ * nfm_reset_round_trips). Age in whole sweeps = floor((sweeps * N - t_last) / N), t_last in
+ * attempt stamps. device_flags: NULL or a device buffer of nfm_n_walkers() bytes (1 flagged,
+ * 0 not; written on the context's stream); *host_count: the number flagged (the call waits for
+ * the stream). window_sweeps = 0 flags every walker. EINVAL on a null count. */
+nfm_status nfm_stuck_walkers(nfm_ctx* ctx, uint64_t window_sweeps, uint8_t* device_flags, int64_t* host_count);
 
 /* Weight iteration on the device (Sec. II: the DOS estimate is iterated once per realization,
  * with power-law shaped targets, and reused by every ensemble). Profiles: 0 flat (Eq. (3)),
@@ -329,7 +339,8 @@ nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
 /* Autotuner for mixed batches (no passage of the paper: a launch-configuration search). Times
  * every candidate tuning (speculation off/on x sweeps per launch {16, 64, 256, 1024} x {per-size
  * launches without and (no speculation) with the generator wave, persistent queue with as many
- * workgroups as fit, 4 or 8 per CU, split}) for calib_sweeps
+ * workgroups as fit, 4 or 8 per CU, split}, and at 256 sweeps per launch the two persistent forms
+ * with the histogram's extent set (window, every level) instead of automatic) for calib_sweeps
  * sweeps on the batch itself, then restores spins, walker state and histograms, so the
  * calibration leaves no trace in the results (the sweep counter does not move). The fastest
  * candidate (spin-flip attempts per second) is applied and returned in *best. Results are cached

@@ -179,6 +179,7 @@ struct nfm_ctx {
   int pt_M = 0;                            // parallel tempering: slots per set
   std::vector<double> pt_T;                // per realization kMaxReplicas temperatures (slot order)
   uint64_t pt_t_reset = 0;                 // sweep counter when the exchange counters were cleared
+  uint64_t rt_reset = 0;                   // sweep counter when the round-trip state was last cleared
   int32_t* d_pt_slot() { return (int32_t*)(ws + lay.pt_slot); }
   uint64_t* d_pt_acc() { return (uint64_t*)(ws + lay.pt_acc); }
   uint32_t* d_pt_metro() { return (uint32_t*)(ws + lay.pt_metro); }
@@ -523,6 +524,7 @@ nfm_status nfm_compute_energies(nfm_ctx* c) {
   hipError_t e = nfm::launch_energy(c->d_reals(), c->n_real, max_walkers(c), c->d_jabi(), c->d_spins(),
                                     c->walker_state(), c->stream);
   if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("energy: ") + hipGetErrorString(e));
+  c->rt_reset = c->sweeps;
   return NFM_OK;
 }
 
@@ -835,7 +837,7 @@ nfm_status nfm_sync(nfm_ctx* c) {
 // holds offsets, not addresses, so the copy is valid at any workspace address).
 namespace {
 constexpr char kCkptMagic[8] = {'N', 'F', 'M', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t kCkptVersion = 3;   // 3: the traced walker range is part of the header
+constexpr uint32_t kCkptVersion = 4;   // 4: the sweep of the last round-trip clearing is part of the header
 struct CkptHeader {
   char magic[8];
   uint32_t version, n_real;
@@ -845,6 +847,7 @@ struct CkptHeader {
   int32_t schedule, waves_per_cu, rec_ready, pt_M, wl_ready;
   uint64_t sweeps, trace_t0, pt_t_reset;
   int64_t trace_slots, trace_w0, trace_nw;
+  uint64_t rt_reset;
 };
 
 // FNV-1a over every realization's size, walker count and id: the layout of the workspace
@@ -904,6 +907,7 @@ nfm_status nfm_checkpoint(nfm_ctx* c, void* host_blob, size_t capacity) {
   h.trace_slots = c->trace_slots;
   h.trace_w0 = c->trace_w0;
   h.trace_nw = c->trace_nw;
+  h.rt_reset = c->rt_reset;
   char* out = (char*)host_blob;
   std::memcpy(out, &h, sizeof(h));
   double* T = (double*)(out + sizeof(h));
@@ -927,7 +931,7 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
       h.disorder_seed != c->disorder_seed || h.walker_seed != c->walker_seed || h.trace_slots != c->trace_slots)
     return fail(c, NFM_EINVAL, "restore: checkpoint of a different batch (sizes, walkers, ids, seeds or trace)");
   if (size < ckpt_bytes(c)) return fail(c, NFM_ESIZE, "restore: checkpoint truncated");
-  if (h.sweeps > (uint64_t)UINT32_MAX || h.trace_t0 > h.sweeps || h.pt_t_reset > h.sweeps)
+  if (h.sweeps > (uint64_t)UINT32_MAX || h.trace_t0 > h.sweeps || h.pt_t_reset > h.sweeps || h.rt_reset > h.sweeps)
     return fail(c, NFM_EINVAL, "restore: sweep counters out of range");
   if (h.trace_w0 < 0 || h.trace_nw < 0 || h.trace_w0 + h.trace_nw > c->lay.total_walkers || h.trace_cap < 0 ||
       (h.trace_nw > 0 && h.trace_cap > 0 && h.trace_nw > h.trace_slots / h.trace_cap))
@@ -956,6 +960,7 @@ nfm_status nfm_restore(nfm_ctx* c, const void* host_blob, size_t size) {
     c->trace_w0 = h.trace_w0;
     c->trace_nw = h.trace_nw;
     c->pt_t_reset = h.pt_t_reset;
+    c->rt_reset = h.rt_reset;
     return pull_reals(c);   // table rows, bounds and energies base as the checkpoint had them
   })
 }
@@ -976,6 +981,23 @@ nfm_status nfm_reset_round_trips(nfm_ctx* c) {
   NFM_HIP(c, hipMemsetAsync(ws.rt_state, 0, 4 * (size_t)W, c->stream));
   NFM_HIP(c, hipMemsetAsync(ws.new_min, 0, 4 * (size_t)W, c->stream));
   NFM_HIP(c, hipMemsetAsync(c->ws + c->lay.ws_u64, 0, 8 * 3 * (size_t)W, c->stream));
+  c->rt_reset = c->sweeps;
+  return NFM_OK;
+}
+
+nfm_status nfm_stuck_walkers(nfm_ctx* c, uint64_t window_sweeps, uint8_t* device_flags, int64_t* host_count) {
+  NFM_GUARD(c);
+  if (!host_count) return fail(c, NFM_EINVAL, "stuck_walkers: null count");
+  // the count sits past the two work-queue counters of the persistent launches
+  uint32_t* d_count = (uint32_t*)(c->ws + c->lay.counter) + 32;
+  NFM_HIP(c, hipMemsetAsync(d_count, 0, 4, c->stream));
+  hipError_t e = nfm::launch_stuck(c->d_reals(), c->n_real, c->walker_state(), c->sweeps, c->rt_reset, window_sweeps,
+                                   device_flags, d_count, c->stream);
+  if (e != hipSuccess) return fail(c, NFM_EDEVICE, std::string("stuck_walkers: ") + hipGetErrorString(e));
+  uint32_t n = 0;
+  NFM_HIP(c, hipMemcpyAsync(&n, d_count, 4, hipMemcpyDeviceToHost, c->stream));
+  NFM_HIP(c, hipStreamSynchronize(c->stream));
+  *host_count = (int64_t)n;
   return NFM_OK;
 }
 
@@ -1235,7 +1257,14 @@ nfm_status nfm_autotune(nfm_ctx* c, int32_t calib_sweeps, const char* cache_path
         for (int wpc : {4, 8})
           if ((int64_t)wpc * c->n_cu < l.total_waves) cand.push_back(nfm_tuning{spec, ch, 1, wpc, 0, 0});
         SplitPart big, rest;
-        if (plan_split(c, &big, &rest)) cand.push_back(nfm_tuning{spec, ch, 2, 0, 0, 0});
+        const bool split = plan_split(c, &big, &rest);
+        if (split) cand.push_back(nfm_tuning{spec, ch, 2, 0, 0, 0});
+        // the on-chip histogram's extent, explicitly (window, every level) for the persistent forms
+        if (ch == 256)
+          for (int hm : {1, 2}) {
+            cand.push_back(nfm_tuning{spec, ch, 1, 0, hm, 0});
+            if (split) cand.push_back(nfm_tuning{spec, ch, 2, 0, hm, 0});
+          }
       }
     hipEvent_t e0, e1;
     NFM_HIP(c, hipEventCreate(&e0));

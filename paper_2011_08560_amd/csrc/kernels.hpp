@@ -26,6 +26,9 @@ hipError_t launch_unpack_spins(const RealInfo* reals, int r, int wl0, int count,
 hipError_t launch_energy(const RealInfo* reals, int n_real, int max_walkers, const uint32_t* jabi,
                          const uint32_t* spins, WalkerState ws, hipStream_t s);
 hipError_t launch_reduce_real(const RealInfo* reals, int n_real, WalkerState ws, RealStatsDev* out, hipStream_t s);
+// walkers without a completed round trip in the last `window` sweeps (flags optional; count added)
+hipError_t launch_stuck(const RealInfo* reals, int n_real, WalkerState ws, uint64_t now, uint64_t since,
+                        uint64_t window, uint8_t* flags, uint32_t* count, hipStream_t s);
 // per-realization round-trip times and their population mean over [r0, r0 + count)
 struct RtSummaryDev {        // same layout as nfm_rt_summary
   double tau_pop;

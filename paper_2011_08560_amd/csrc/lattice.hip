@@ -281,6 +281,34 @@ hipError_t launch_reduce_real(const RealInfo* reals, int n_real, WalkerState ws,
   return hipGetLastError();
 }
 
+// Stuck-walker watch: a walker is flagged when its last completed round trip (without one: the
+// clearing of its round-trip state, at sweep `since`) lies `window` or more sweeps before the
+// sweep counter `now`. Stamps count attempts (sweep t, attempt a: t N + a + 1), so the age in
+// whole sweeps is floor((now N - last) / N). One block per realization; flags (optional) per
+// walker, the number flagged added to *count.
+__global__ void k_stuck(const RealInfo* __restrict__ reals, WalkerState ws, uint64_t now, uint64_t since,
+                        uint64_t window, uint8_t* __restrict__ flags, uint32_t* __restrict__ count) {
+  const RealInfo ri = reals[blockIdx.x];
+  const uint64_t N = (uint64_t)ri.N;
+  const uint64_t end = now * N;
+  uint32_t n = 0;
+  for (int wl = threadIdx.x; wl < ri.walkers; wl += blockDim.x) {
+    const int64_t g = ri.walker_off + wl;
+    const uint64_t last = ws.rt_count[g] > 0 ? ws.t_last[g] : since * N;
+    const uint64_t age = last < end ? (end - last) / N : 0;
+    const bool stuck = age >= window;
+    if (flags) flags[g] = stuck ? 1 : 0;
+    n += stuck ? 1u : 0u;
+  }
+  if (n) atomicAdd(count, n);
+}
+
+hipError_t launch_stuck(const RealInfo* reals, int n_real, WalkerState ws, uint64_t now, uint64_t since,
+                        uint64_t window, uint8_t* flags, uint32_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_stuck, dim3(n_real), dim3(256), 0, s, reals, ws, now, since, window, flags, count);
+  return hipGetLastError();
+}
+
 // Round-trip times (Sec. III): tau_i = (sum of completed-trip time) / (number of trips) / N in
 // sweeps, censored (NaN) below min_trips trips; tau_pop = mean of the uncensored tau_i. One block;
 // the sum runs as a fixed-shape tree, so the result does not depend on scheduling.

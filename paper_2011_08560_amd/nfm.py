@@ -25,15 +25,16 @@ class NfmError(RuntimeError):
         self.status = status
 
 
-def check_device_tensor(t, device, shape, what: str):
-    """Refuse (ValueError) a tensor the kernels cannot take as a float32 row-major array of
-    exactly `shape` on `device` (a torch.device): every pointer handed to the library must
-    cover what its kernels read and write."""
+def check_device_tensor(t, device, shape, what: str, dtype=None):
+    """Refuse (ValueError) a tensor the kernels cannot take as a row-major array of `dtype`
+    (default float32) of exactly `shape` on `device` (a torch.device): every pointer handed to
+    the library must cover what its kernels read and write."""
     import torch
+    dtype = torch.float32 if dtype is None else dtype
     if not isinstance(t, torch.Tensor):
         raise ValueError(f"{what}: a torch tensor is required, got {type(t).__name__}")
-    if t.dtype != torch.float32:
-        raise ValueError(f"{what}: dtype float32 required, got {t.dtype}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {dtype} required, got {t.dtype}")
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"{what}: shape {tuple(shape)} required, got {tuple(t.shape)}")
     if not t.is_contiguous():
@@ -140,6 +141,7 @@ def lib():
         "nfm_restore": (i32, [vp, vp, sz]),
         "nfm_set_histograms": (i32, [vp, vp]),
         "nfm_reset_round_trips": (i32, [vp]),
+        "nfm_stuck_walkers": (i32, [vp, u64, vp, C.POINTER(i64)]),
         "nfm_rec_init": (i32, [vp, i32, C.c_double, C.c_double]),
         "nfm_rec_update": (i32, [vp, C.c_double, vp]),
         "nfm_rec_production": (i32, [vp, i32, C.c_double, C.c_double]),
@@ -477,6 +479,21 @@ class Batch:
 
     def reset_round_trips(self):
         self._check(self._lib.nfm_reset_round_trips(self.ctx), "reset_round_trips")
+
+    def stuck_walkers(self, window_sweeps: int, flags=None) -> int:
+        """Walkers without a completed round trip in the last window_sweeps sweeps
+        (nfm_stuck_walkers): their number; flags, if given, a uint8 device tensor of n_walkers
+        entries, receives 1 for each flagged walker."""
+        import torch
+        window = int(window_sweeps)
+        if window < 0:
+            raise ValueError("stuck_walkers: window_sweeps must be >= 0")
+        ptr = C.c_void_p(None)
+        if flags is not None:
+            ptr = check_device_tensor(flags, self.device, (self.n_walkers,), "stuck_walkers: flags", torch.uint8)
+        n = C.c_int64()
+        self._check(self._lib.nfm_stuck_walkers(self.ctx, window, ptr, C.byref(n)), "stuck_walkers")
+        return int(n.value)
 
     def rec_init(self, profile: int = PROFILE_FLAT, pl_dE: float = 1.0, pl_alpha: float = 0.0):
         self._check(self._lib.nfm_rec_init(self.ctx, profile, pl_dE, pl_alpha), "rec_init")
