@@ -334,6 +334,12 @@ def main():
     kernel = b.last_kernel()   # the form the library chose for the timed launches
     spl = tn["sweeps_per_launch"]
     traffic = counter_summary(args.config, kernel, spl, "traffic_bytes_per_launch") if S % spl == 0 else None
+    if traffic is None:
+        # a summary that fitted per-launch traffic over two launch sizes serves any launch size
+        fixed = counter_summary(args.config, kernel, None, "traffic_bytes_fixed_per_launch")
+        per_sweep = counter_summary(args.config, kernel, None, "traffic_bytes_per_sweep")
+        if fixed is not None and per_sweep is not None:
+            traffic = fixed + per_sweep * S / launches_per_step
     # instructions per attempt do not depend on the launch size (counters of one launch size serve)
     valu = counter_summary(args.config, kernel, None, "valu_lane_instructions_per_attempt")
 
