@@ -667,8 +667,10 @@ static nfm_status muca_launches(nfm_ctx* c, uint64_t t0, uint64_t n_sweeps, int 
       // at most half the SIMDs go to the largest lattices; the rest of the queue over the SIMDs left
       const int64_t simds = 4LL * c->n_cu;
       const int64_t grid_big = std::max<int64_t>(1, std::min<int64_t>(big.n, simds / 2));
-      const int per_simd = std::max(1, nfm::queue_blocks_per_cu(spec, rest.lds_rows, rest.K, hist_mode, rest.maxl) / 4);
-      const int64_t grid_rest = std::max<int64_t>(1, std::min<int64_t>(rest.n, per_simd * (simds - grid_big)));
+      // the other sizes: as many workgroups as fit on the whole device (those that find no room
+      // beside the largest lattices' waves start when a slot frees and take what the queue has left)
+      const int per_cu = std::max(1, nfm::queue_blocks_per_cu(spec, rest.lds_rows, rest.K, hist_mode, rest.maxl));
+      const int64_t grid_rest = std::max<int64_t>(1, std::min<int64_t>(rest.n, (int64_t)per_cu * c->n_cu));
       NFM_HIP(c, hipEventRecord(c->split_fork, c->stream));
       hipError_t e = nfm::launch_muca_queue(a, order, (int)big.n, counter, (int)grid_big, c->n_cu, big.lds_rows, big.K,
                                             hist_mode, spec, c->stream, big.maxl, true);
