@@ -571,7 +571,7 @@ class Batch:
         self._check(self._lib.nfm_get_tuning(self.ctx, t.ctypes.data), "get_tuning")
         return dict(zip(TUNING_FIELDS, (int(x) for x in t)))
 
-    def autotune(self, calib_sweeps: int = 256, cache_path: Optional[str] = None, max_results: int = 64):
+    def autotune(self, calib_sweeps: int = 256, cache_path: Optional[str] = None, max_results: int = 128):
         """Time the candidate launch configurations on this batch (state restored afterwards),
         apply the fastest. Returns (best tuning dict, list of (tuning dict, attempts/s))."""
         res = np.zeros(max_results, TUNE_RESULT_DTYPE)
