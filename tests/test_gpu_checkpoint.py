@@ -87,6 +87,36 @@ def test_resume_multicanonical(nfm):
     b.close()
 
 
+def test_resume_across_launch_forms(nfm):
+    """A run under the split persistent launch, checkpointed mid-round and resumed under the
+    per-size launches (and the reverse), continues exactly as the uninterrupted run: the launch
+    form travels with the checkpoint but does not change results."""
+    Ls = [4, 8, 6, 4, 8]
+    print("checkpoint: across launch forms Ls", Ls, flush=True)
+    for first, second in ((dict(schedule=2, sweeps_per_launch=16), dict(schedule=0, sweeps_per_launch=0)),
+                          (dict(schedule=0, sweeps_per_launch=0), dict(schedule=2, sweeps_per_launch=9))):
+        a = _batch(nfm, Ls)
+        a.init_couplings()
+        a.init_spins()
+        a.compute_energies()
+        a.rec_init(nfm.PROFILE_POWER, 96.0, -3.6)
+        a.set_tuning(**first)
+        a.run_sweeps(40)
+        a.rec_update(0.5)
+        a.run_sweeps(21)
+        blob = a.checkpoint()
+        _continue_muca(a)
+        want = _state(a, Ls)
+        b = _batch(nfm, Ls)
+        b.restore(blob)
+        assert b.get_tuning()["schedule"] == first["schedule"]
+        b.set_tuning(**second)
+        _continue_muca(b)
+        _equal(_state(b, Ls), want)
+        a.close()
+        b.close()
+
+
 def _continue_pt(b, M):
     b.pt_run_sweeps(41)
     b.sync()
