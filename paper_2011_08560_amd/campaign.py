@@ -211,23 +211,37 @@ def compare(L, n_real, methods=METHODS, min_trips=100, iter_sweeps=None, f_tol=0
 
 
 def scan(L, n_real, dEs, alphas, min_trips=100, iter_sweeps=None, f_tol=0.5, n_max=60, chunk=None, cap=None,
-         first_id=0, log=None):
-    """Population mean round-trip time of the power-law ensemble over a (dE, alpha) grid."""
+         first_id=0, log=None, eps=1e-4, blocks=0):
+    """Population mean round-trip time of the power-law ensemble over a (dE, alpha) grid, and each
+    grid point's ratios r (Table I's r_pop and r_eps, Sec. V) against the first grid point with
+    alpha = 0 (the flat target; else the first grid point), over the realizations uncensored at
+    both, with jackknife errors. The round-trip times are returned under "tau" as well."""
     iter_sweeps = iter_sweeps or 1000 * L * L
     chunk = chunk or 50 * L ** 3
     cap = cap or 1000 * chunk
     b = make_batch([L] * n_real, first_real_id=first_id)
     converge(b, iter_sweeps, f_tol, n_max, log)
-    grid = []
+    grid, taus = [], []
     for dE in dEs:
         for a in alphas:
             tau, done = production(b, "pl", min_trips, chunk, cap, pl=(dE, a), log=log)
+            tau = np.asarray(tau, float)
             ok = np.isfinite(tau)
             grid.append({"dE": dE, "alpha": a, "tau_pop": float(tau[ok].mean()) if ok.any() else None,
                          "median": float(np.median(tau[ok])) if ok.any() else None,
                          "censored": int((~ok).sum()), "sweeps": done})
+            taus.append(tau)
     b.close()
-    return {"L": L, "realizations": n_real, "min_trips": min_trips, "grid": grid}
+    ref = next((i for i, g in enumerate(grid) if g["alpha"] == 0), 0)
+    for i, g in enumerate(grid):
+        both = np.isfinite(taus[i]) & np.isfinite(taus[ref]) & (taus[i] > 0) & (taus[ref] > 0)
+        g["paired"] = int(both.sum())
+        if i != ref and both.sum() >= 3:
+            r = nfm.relative_performance(taus[i][both], taus[ref][both], eps=eps, method=0, blocks=blocks)
+            g["r_vs_reference"] = {k: r[k] for k in ("r_pop", "r_pop_err", "r_eps", "r_eps_err", "blocks")}
+    return {"L": L, "realizations": n_real, "min_trips": min_trips, "grid": grid,
+            "reference": {"dE": grid[ref]["dE"], "alpha": grid[ref]["alpha"]},
+            "tau": {f"dE{g['dE']:g}_a{g['alpha']:g}": t for g, t in zip(grid, taus)}}
 
 
 def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0.8, wl_ln_f0=None, wl_final=None,
@@ -411,7 +425,11 @@ def main(argv=None):
                 rec["seed_network"] = net
         elif args.scan_dE and args.scan_alpha:
             rec = scan(L, args.real, args.scan_dE, args.scan_alpha, args.min_trips, args.iter_sweeps or None,
-                       args.f_tol, args.n_max, args.chunk or None, args.cap or None, args.first_id, log)
+                       args.f_tol, args.n_max, args.chunk or None, args.cap or None, args.first_id, log,
+                       eps=args.eps, blocks=args.blocks)
+            tau = rec.pop("tau")
+            if args.save_tau:
+                np.savez(args.save_tau, **{f"tau_{k}": t for k, t in tau.items()}, L=np.int64(L))
         else:
             rec = compare(L, args.real, args.methods, args.min_trips, args.iter_sweeps or None, args.f_tol,
                           args.n_max, args.chunk or None, args.cap or None, args.first_id, args.eps, args.blocks, log,
