@@ -232,6 +232,17 @@ def scan(L, n_real, dEs, alphas, min_trips=100, iter_sweeps=None, f_tol=0.5, n_m
                          "censored": int((~ok).sum()), "sweeps": done})
             taus.append(tau)
     b.close()
+    ref = scan_ratios(grid, taus, eps, blocks)
+    return {"L": L, "realizations": n_real, "min_trips": min_trips, "grid": grid,
+            "reference": {"dE": grid[ref]["dE"], "alpha": grid[ref]["alpha"]},
+            "tau": {f"dE{g['dE']:g}_a{g['alpha']:g}": t for g, t in zip(grid, taus)}}
+
+
+def scan_ratios(grid, taus, eps=1e-4, blocks=0):
+    """Adds to each grid point the number of realizations uncensored at it and at the reference
+    (the first point with alpha = 0, else the first point) and, for the others, r_pop and r_eps
+    against the reference over those realizations (Sec. V, Table I's ratios, jackknife errors).
+    Returns the reference's index."""
     ref = next((i for i, g in enumerate(grid) if g["alpha"] == 0), 0)
     for i, g in enumerate(grid):
         both = np.isfinite(taus[i]) & np.isfinite(taus[ref]) & (taus[i] > 0) & (taus[ref] > 0)
@@ -239,9 +250,7 @@ def scan(L, n_real, dEs, alphas, min_trips=100, iter_sweeps=None, f_tol=0.5, n_m
         if i != ref and both.sum() >= 3:
             r = nfm.relative_performance(taus[i][both], taus[ref][both], eps=eps, method=0, blocks=blocks)
             g["r_vs_reference"] = {k: r[k] for k in ("r_pop", "r_pop_err", "r_eps", "r_eps_err", "blocks")}
-    return {"L": L, "realizations": n_real, "min_trips": min_trips, "grid": grid,
-            "reference": {"dE": grid[ref]["dE"], "alpha": grid[ref]["alpha"]},
-            "tau": {f"dE{g['dE']:g}_a{g['alpha']:g}": t for g, t in zip(grid, taus)}}
+    return ref
 
 
 def estimators(L, n_real, sweeps, f_tol=0.5, n_max=60, wl_sweeps=None, wl_flat=0.8, wl_ln_f0=None, wl_final=None,

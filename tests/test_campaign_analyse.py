@@ -73,3 +73,30 @@ def test_analyse_groups_files_by_size(tmp_path):
         r = rec["by_L"][L]["analysis"]["methods"]["flat"]["r"]
         assert r["r_pop"] == pytest.approx(2.0, rel=1e-12)
     assert "xi = " in out.stderr and "L=6" in out.stderr
+
+
+def test_scan_ratios_against_the_flat_point():
+    """The exponent scan's ratios: reference = the first grid point with alpha = 0 (not the first
+    point), each other point paired with it over the realizations uncensored at both, the ratios
+    as the oracle computes them on that paired sample."""
+    from paper_2011_08560_amd import campaign
+    rng = np.random.default_rng(9)
+    n = 40
+    flat = sst.genextreme(-0.7, loc=200.0, scale=70.0).rvs(n, random_state=rng)
+    half = sst.genextreme(-0.5, loc=90.0, scale=30.0).rvs(n, random_state=rng)
+    steep = sst.genextreme(-0.9, loc=900.0, scale=300.0).rvs(n, random_state=rng)
+    flat[3] = np.nan
+    steep[[7, 8]] = np.nan
+    grid = [{"dE": 1.0, "alpha": -0.5}, {"dE": 1.0, "alpha": 0.0}, {"dE": 1.0, "alpha": -2.0}]
+    ref = campaign.scan_ratios(grid, [half, flat, steep], eps=1e-4, blocks=4)
+    assert ref == 1
+    assert "r_vs_reference" not in grid[1]
+    for i, t in ((0, half), (2, steep)):
+        ok = np.isfinite(t) & np.isfinite(flat)
+        assert grid[i]["paired"] == int(ok.sum())
+        want = S.relative_performance(t[ok], flat[ok], eps=1e-4, method=0, blocks=4)
+        got = grid[i]["r_vs_reference"]
+        assert got["r_pop"] == pytest.approx(want["r_pop"], rel=1e-12)
+        assert got["r_pop_err"] == pytest.approx(want["r_pop_err"], rel=1e-9)
+        assert got["r_eps"] == pytest.approx(want["r_eps"], rel=1e-4)
+    assert grid[0]["paired"] == n - 1 and grid[2]["paired"] == n - 3
