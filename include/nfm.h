@@ -510,7 +510,7 @@ const char* nfm_stats_last_error(void);
 
 /* ---------------------------------------------------------------------------------------
  * Learned start of the weight iteration (not in the paper: a model that guesses the density of
- * states from the couplings, checked by the recursion of Sec. II, which remains the judge).
+ * states from the couplings, checked by the recursion of Sec. II, which decides the final estimate).
  *
  * nfm_set_canonical: canonical Metropolis tables at temperature T > 0 for every realization
  *   (lnW = -E/T; the two top levels are given and the lowest step continues below, which is

@@ -4,7 +4,7 @@ The weight iteration of Sec. II (Muller, Schnabel, Janke) starts from W = 1 and 
 rounds before the walkers reach the lowest energies and the histogram flattens. Here a small
 network guesses ln Omega(E) of a realization from its couplings and a short T = 2 canonical run;
 the guess seeds the recursion as a prior on the DOS steps (nfm_rec_seed_grid), and the
-recursion remains the judge. Every step runs in the library's kernels: the canonical run, the
+recursion decides the final estimate. Every step runs in the library's kernels: the canonical run, the
 features, the recursion, the targets, the network's training (FP32) and inference (BF16); torch
 only holds device tensors and shuffles minibatches.
 

@@ -169,7 +169,7 @@ def test_recursion_full_size(nfm, orc, bench, config, form, n_sample):
     assert b.last_kernel() == form
     hists = _compare_round(b, orc, refs, tabs, 2000, W)
     _update_and_compare(b, orc, refs, tabs, hists)
-    print("full size:", config, "round 2", flush=True)
+    print("full size:", config, "second weight round", flush=True)
     tabs = _sync_tables(b, orc, refs, profile)
     b.run_sweeps(1000)
     _compare_round(b, orc, refs, tabs, 1000, W)
