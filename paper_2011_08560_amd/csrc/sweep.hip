@@ -77,44 +77,47 @@ __device__ __forceinline__ void unpack(typename Geo<L>::PW v, uint32_t* w) {
 __device__ __forceinline__ int floor_div4(int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); }
 __device__ __forceinline__ int ceil_div4(int a) { return -floor_div4(-a); }
 
-// Bookkeeping window: while lo <= B <= hi an attempt cannot change the minimum, the
-// new-minimum flag or the round-trip state, so the exact update of Sec. III runs only for
-// groups of attempts in which B left the window. B = (k - row0) * 32 for level k.
+// Bookkeeping window of the round-trip state: while lo <= B <= hi an attempt cannot change it
+// (B = (k - row0) * 32 for level k). The walker's minimum and new-minimum flag do not depend on the
+// order of the attempts, so they are taken from each group's lowest B instead; only a group in
+// which some walker reached the bound its state waits for is replayed in order.
 struct Window {
   int lo, hi;
 };
 
-__device__ __forceinline__ Window make_window(int Bmin, int state, int newmin, int Bbot, int Btop, int Bnm) {
+// Groups of four attempts between two window checks of an L x L x L lattice. Each check costs the
+// extremes of the levels since the last one, a compare and a branch, and a replay covers every
+// attempt since then: a lone wave on its SIMD (the largest lattices) gains from longer intervals,
+// several waves per SIMD whose walkers often reach a bound (small lattices, first rounds) from
+// shorter ones.
+template <int L>
+constexpr int check_groups() { return L >= 12 ? 8 : L >= 10 ? 4 : 2; }
+
+__device__ __forceinline__ Window make_window(int state, int Bbot, int Btop) {
   constexpr int INF = 1 << 29;
-  int lo = Bmin;
-  if (state == 1) lo = max(lo, Bbot + 32);
-  if (!newmin) lo = max(lo, Bnm + 32);
   Window w;
-  w.lo = lo;
-  w.hi = (state != 1) ? Btop - 32 : INF;  // lo > hi: every attempt is examined
+  w.lo = (state == 1) ? Bbot + 32 : -INF;   // at or after the top: waiting for the bottom
+  w.hi = (state == 1) ? INF : Btop - 32;    // before the first top, or after a bottom: for the top
   return w;
 }
 
-// Exact bookkeeping of one attempt (Sec. III): minimum, new-minimum flag, round trips.
+// Exact round-trip bookkeeping of one attempt (Sec. III): E >= e_top <=> B >= Btop and
+// E <= e_bot <=> B <= Bbot.
 struct Track {
   int Bmin, state, newmin;
   uint32_t trips;
   uint64_t t_first, t_last;
 };
 
-__device__ __forceinline__ void track_attempt(Track& tr, int B, uint64_t tau, int e_base, int row0, int e_bot,
-                                              int e_top) {
-  const int E = e_base + 4 * ((B >> 5) + row0);
-  if (B < tr.Bmin) tr.Bmin = B;
-  if (E < e_bot) tr.newmin = 1;
-  if (E >= e_top) {
+__device__ __forceinline__ void track_attempt(Track& tr, int B, uint64_t tau, int Bbot, int Btop) {
+  if (B >= Btop) {
     if (tr.state == 2) {
       tr.trips += 1;
       tr.t_last = tau;
     }
     if (tr.state == 0) tr.t_first = tau;
     tr.state = 1;
-  } else if (E <= e_bot && tr.state == 1) {
+  } else if (B <= Bbot && tr.state == 1) {
     tr.state = 2;
   }
 }
@@ -396,7 +399,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
   const int Bbot = (floor_div4(e_bot - e_base) - row0) * 32;   // E <= e_bot  <=> B <= Bbot
   const int Bnm = (ceil_div4(e_bot - e_base) - 1 - row0) * 32; // E <  e_bot  <=> B <= Bnm
   Window win;
-  if constexpr (!PT) win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+  if constexpr (!PT) win = make_window(tr.state, Bbot, Btop);
   int R = clamp_row(B, Bmax);   // the table row in use: B clamped to the stored rows
   int vBmax;                    // Bmax in a vector register (an operand of the decision sequence)
   asm volatile("v_mov_b32 %0, %1" : "=v"(vBmax) : "s"(Bmax));
@@ -539,8 +542,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
         // Acceptance bits are shifted into F in site order, with a zero for every bit of a
         // field beyond the row's H sites, and applied to the plane-colour string once per word.
         uint32_t F = 0;
-        // levels after each attempt since the last window check (two groups of four)
-        int Bq[8];
+        // levels after each attempt since the last window check (kCheckGroups groups of four)
+        constexpr int kCheckGroups = check_groups<L>();
+        int Bq[4 * kCheckGroups];
         // speculative form: the pair for site 0 of the block is loaded at the block's start
         uint32_t p_rej = 0, p_acc = 0;
         int Racc_prev = R;
@@ -647,7 +651,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
               }
               hi_cur = hi_next;
             }
-            Bq[4 * (g & 1) + i] = B;
+            Bq[4 * (g % kCheckGroups) + i] = B;
             // end of a row inside the word: zeros for the field's unused bits; end of the word
             // (or of the string): apply the flips
             const bool last_in_word = (q + 1 == Q) || (((((q + 1) / H) * FB + (q + 1) % H) >> 5) != w);
@@ -665,25 +669,29 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int wave) {
             if (n_att == 3) philox_rounds<8, 10>(pr, kv);
           }
           if constexpr (!PT) {
-            // Every second group (and at the block's end): did an attempt since the last check
-            // leave the window? Then replay those attempts' bookkeeping exactly.
-            if ((g & 1) == 1 || g + 1 == NG) {
-              const int g0 = g & ~1;                               // first group since the check
+            // Every kCheckGroups-th group (and at the block's end): the minimum and the
+            // new-minimum flag from the lowest level since the last check; if an attempt since
+            // then reached the bound the round-trip state waits for, replay those attempts'
+            // state exactly.
+            if (g % kCheckGroups == kCheckGroups - 1 || g + 1 == NG) {
+              const int g0 = g - g % kCheckGroups;                 // first group since the check
               const int cnt = 4 * (g - g0) + n_att;                // attempts since the check
               int bmin = Bq[0], bmax = Bq[0];
 #pragma unroll
-              for (int k = 1; k < 8; ++k) {
+              for (int k = 1; k < 4 * kCheckGroups; ++k) {
                 if (k >= cnt) break;
                 bmin = min(bmin, Bq[k]);
                 bmax = max(bmax, Bq[k]);
               }
+              tr.Bmin = min(tr.Bmin, bmin);
+              tr.newmin = (bmin <= Bnm) ? 1 : tr.newmin;           // E < e_bot <=> B <= Bnm
               if (bmin < win.lo || bmax > win.hi) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                for (int k = 0; k < 4 * kCheckGroups; ++k) {
                   if (k >= cnt) break;
-                  track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g0 + k), e_base, row0, e_bot, e_top);
+                  track_attempt(tr, Bq[k], tau_blk + (uint64_t)(4 * g0 + k), Bbot, Btop);
                 }
-                win = make_window(tr.Bmin, tr.state, tr.newmin, Bbot, Btop, Bnm);
+                win = make_window(tr.state, Bbot, Btop);
               }
             }
           }
