@@ -176,3 +176,24 @@ def test_small_lattice_queue_and_split_fallback(nfm, orc):
             b.run_sweeps(n)
             _same(_state(b), want)
             b.close()
+
+
+def test_split_with_more_large_waves_than_its_share(nfm, orc):
+    """More waves of the largest size than half the SIMDs: the SIMD-exclusive part is a
+    persistent queue over more items than workgroups; bit for bit as the per-size launches."""
+    import torch
+    n_simd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    Ls = [12] * (n_simd // 2 + 9) + [4, 6, 4]
+    n = 3
+    print("split: largest size", Ls.count(12), "waves for", n_simd // 2, "SIMDs", flush=True)
+    ref = _batch(nfm, orc, Ls, n)
+    ref.set_tuning(schedule=0)
+    ref.run_sweeps(n)
+    want = _state(ref)
+    ref.close()
+    b = _batch(nfm, orc, Ls, n)
+    b.set_tuning(schedule=2, sweeps_per_launch=2)
+    b.run_sweeps(n)
+    assert b.last_kernel() == "k_sweeps_queue_solo"
+    _same(_state(b), want)
+    b.close()
