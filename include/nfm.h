@@ -340,7 +340,7 @@ nfm_status nfm_get_tuning(const nfm_ctx* ctx, nfm_tuning* tuning);
  * every candidate tuning (speculation off/on x sweeps per launch {16, 64, 256, 1024} x {per-size
  * launches without and (no speculation) with the generator wave, persistent queue with as many
  * workgroups as fit, 4 or 8 per CU, split}, and at 256 sweeps per launch the two persistent forms
- * with the histogram's extent set (window, every level) instead of automatic) for calib_sweeps
+ * with the histogram as the window alone instead of automatic) for calib_sweeps
  * sweeps on the batch itself, then restores spins, walker state and histograms, so the
  * calibration leaves no trace in the results (the sweep counter does not move). The fastest
  * candidate (spin-flip attempts per second) is applied and returned in *best. Results are cached
